@@ -1,0 +1,191 @@
+"""Benchmark: block Krylov-Schur hot path on one MI355X.
+
+Workload: R-MAT scale 22 (4,194,304 vertices, edge factor 16,
+a/b/c/d = .57/.19/.19/.05, seed 22), symmetrised, deduplicated, self-loops
+dropped, 0/1 pattern CSR relabelled by degree.  One step = one full block
+Krylov-Schur solve for the 8 largest-magnitude eigenpairs, block 4,
+subspace 48, FP32 storage, tol 1e-6, random start (every row of the hot
+path: sparse products, CGS2 Gram/updates, block QR, Rayleigh-Ritz, restarts
+and the FP64 final check).
+
+value = sparse work of the solve (nnz x columns multiplied) / solve time,
+in GEdge*col/s.  The JSON line also carries the SpMM-only sweep over block
+widths 1, 2, 4, 8, 16 (FP32), the roofline of the dominant kernel and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "SpMM GEdge·col/s & % HBM roofline; time-to-8-eigs learned vs random start"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def spmm_bytes(n, nnz, b, s):
+    return 4.0 * nnz + 8.0 * (n + 1) + 2.0 * n * b * s
+
+
+def time_spmm(P, A, b, dtype, stream, reps):
+    import torch
+    X = torch.randn((A.n, b), device="cuda", dtype=torch.float32).to(dtype)
+    Y = torch.empty_like(X)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            P.fe_spmm(A, X, Y, stream=stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            P.fe_spmm(A, X, Y, stream=stream)
+        e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def cpu_baseline(n, s, d, nnz, budget_s=25.0):
+    """The oracle as it stands on this host: the first full expansion of a
+    solve (m/b = 12 sparse products of width 4 with CGS2 and block QR, no
+    restart) on the same graph, all host cores, FP64."""
+    import numpy as np
+    import fe_synth as S
+    import oracle as O
+    t0 = time.time()
+    rp, ci = O.csr_from_edges(n, s, d)
+    t_csr = time.time() - t0
+    threads = O.max_threads()
+    X0 = S.normal((n, 4), seed=3)
+    t0 = time.time()
+    r = O.krylov_schur(lambda X: O.spmm(rp, ci, X, threads=threads), n, 8, 4, 48, 1e-6, X0,
+                       max_restarts=0)
+    t = time.time() - t0
+    cols = 4 * r.spmm_calls + 8
+    return {"value": nnz * cols / t / 1e9, "unit": "GEdge·col/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first expansion of the same solve: {r.spmm_calls} width-4 products with "
+                      f"CGS2/CholQR2 plus the width-8 final check, FP64, no restart; "
+                      f"{t:.1f} s (oracle CSR build {t_csr:.1f} s not timed)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--spmm-reps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path would "
+              f"shard by row blocks, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import fe_synth as S
+    import paper_1602_01421_amd as P
+
+    P.lib()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    t0 = time.time()
+    n, s, d = S.rmat_edges(args.scale, edge_factor=16, a=0.57, b=0.19, c=0.19, seed=args.scale)
+    t_gen = time.time() - t0
+    t0 = time.time()
+    A = P.fe_csr_build(n, s, d, P.FE_GRAPH_DEFAULT | P.FE_RELABEL_BY_DEGREE)
+    t_build = time.time() - t0
+    log(f"R-MAT scale {args.scale}: n={n} nnz={A.nnz} max_deg={A.max_deg} "
+        f"(generate {t_gen:.1f} s, fe_csr_build {t_build:.1f} s)")
+
+    # SpMM-only sweep (FP32)
+    sweep = []
+    for b in (1, 2, 4, 8, 16):
+        t = time_spmm(P, A, b, torch.float32, stream, args.spmm_reps)
+        by = spmm_bytes(A.n, A.nnz, b, 4)
+        sweep.append({"b": b, "us": t * 1e6, "gedge_col_s": A.nnz * b / t / 1e9,
+                      "gbs": by / t / 1e9, "frac": by / t / 1e9 / HBM_PEAK_GBS})
+        log(f"spmm b={b:2d}: {t*1e6:8.1f} us  {A.nnz*b/t/1e9:8.1f} GEdge*col/s  "
+            f"{by/t/1e9:7.1f} GB/s ({100*by/t/1e9/HBM_PEAK_GBS:.1f}% of HBM)")
+
+    # whole-path steps: one solve each
+    nev, block, m, tol = 8, 4, 48, 1e-6
+
+    def solve(seed, profile=False):
+        return P.fe_krylov_schur(A, nev, block, m, tol, dtype=torch.float32, seed=seed,
+                                 stream=stream, want_vectors=True, profile=profile)
+
+    for w in range(args.warmup):
+        r = solve(100 + w)
+        log(f"warmup solve: status {r.status} restarts {r.restarts} products {r.spmm_calls} "
+            f"{r.t_total:.3f} s")
+    torch.cuda.synchronize()
+    times, cols, results = [], 0, []
+    t_all0 = time.perf_counter()
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = solve(1 + k)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        cols += r.spmm_cols
+        results.append(r)
+        log(f"step {k}: {times[-1]:.3f} s  status {r.status} restarts {r.restarts} "
+            f"products {r.spmm_calls} max resid {r.resid.max():.2e} lambda1 {r.evals[0]:.8g}")
+    t_all = time.perf_counter() - t_all0
+    value = A.nnz * cols / t_all / 1e9
+
+    # per-kernel profile of one more solve (HIP events on the solve's stream)
+    rp = solve(1, profile=True)
+    classes = {"spmm": (rp.t_spmm, rp.bytes_spmm, rp.spmm_calls),
+               "gram": (rp.t_gram, rp.bytes_gram, rp.gram_calls),
+               "update": (rp.t_update, rp.bytes_update, rp.update_calls)}
+    dom = max(classes, key=lambda c: classes[c][0])
+    t_dom, b_dom, calls_dom = classes[dom]
+    achieved = b_dom / t_dom / 1e9
+    log("profile: " + ", ".join(f"{c} {v[0]*1e3:.1f} ms / {v[2]} launches "
+                                 f"({v[1]/max(v[0],1e-12)/1e9:.0f} GB/s)" for c, v in classes.items())
+        + f", other {rp.t_other_dev*1e3:.1f} ms, host {rp.t_host*1e3:.1f} ms, total {rp.t_total*1e3:.1f} ms")
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "launches": calls_dom, "avg_launch_us": t_dom / calls_dom * 1e6,
+            "algorithmic_bytes_per_launch": b_dom / calls_dom}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "GEdge·col/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t_all / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"rmat{args.scale}_krylov_schur_nev8_b4_m48_f32", "scale": args.scale,
+                   "n": A.n, "nnz": A.nnz, "edge_factor": 16, "rmat_abcd": [0.57, 0.19, 0.19, 0.05],
+                   "nev": nev, "block": block, "m": m, "tol": tol, "relabel": "degree"},
+        "roofline": roof,
+        "time_to_8_eigs_s": float(np.median(times)),
+        "solve": {"restarts": [r.restarts for r in results],
+                  "spmm_calls": [r.spmm_calls for r in results],
+                  "max_resid": [float(r.resid.max()) for r in results],
+                  "evals": [float(x) for x in results[-1].evals]},
+        "spmm_sweep": sweep,
+        "build_s": t_build,
+    }
+    if not args.no_cpu:
+        log("timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(n, s, d, A.nnz)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.3f} GEdge*col/s on "
+            f"{out['cpu_baseline']['cores']} threads")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

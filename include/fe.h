@@ -1,0 +1,221 @@
+/*
+ * fe.h -- C ABI of the MI355X block Krylov-Schur hot path.
+ *
+ * The operations follow the paper's statement of the problem:
+ *   - the generic eigen-iteration of its eigensolver-algorithm subsection
+ *     (update the subspace, solve the projected problem, residual of the
+ *     Ritz pairs, convergence test) with the block extension: b vectors per
+ *     step, so the sparse product is a sparse-matrix x dense-block product;
+ *   - the sparse matrix multiplication section (pattern matrix, each nonzero
+ *     adds an input row to an output row);
+ *   - the table of dense operations the eigensolver requires (MvTransMv and
+ *     MvTimesMatAddMv with their alpha/beta scalars) in the vector-subspace
+ *     section;
+ *   - the two-stage reduction for operations whose output is a small matrix
+ *     and the row-interval parallelisation of tall-and-skinny operations
+ *     (the subsection on parallelising matrix operations).
+ *
+ * Conventions
+ *   - Every function returns fe_status and never throws across the ABI.  On a
+ *     non-OK status, fe_last_error() returns a message for the calling thread.
+ *   - "device" pointers are HIP device allocations on the current device;
+ *     "host" pointers are ordinary host memory.
+ *   - Dense tall-and-skinny blocks are row-major with leading dimension equal
+ *     to their width ("packed"): element (i, c) of an n x b block is at
+ *     index i*b + c.  A subspace of k = nblk*b columns is a list of nblk such
+ *     blocks, block j starting blk_stride elements after block j-1.
+ *   - Storage dtypes: FE_F64, FE_F32, FE_BF16 (raw bfloat16 bits, uint16_t).
+ *     Sparse sums accumulate in FP32 (FP64 for FE_F64 storage); Gram and
+ *     update arithmetic is FP64; results are rounded to the storage dtype by
+ *     round-to-nearest-even.
+ *   - Kernels run asynchronously on the HIP stream passed as `hip_stream`
+ *     (hipStream_t cast to void*; NULL = the null stream).  Callers own all
+ *     buffers they pass; the library owns fe_csr handles.
+ *   - Calls on distinct handles/streams may run concurrently.  Calls on one
+ *     fe_csr handle share its split-row scratch and must not overlap in time.
+ */
+#ifndef FE_H
+#define FE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FE_OK = 0,
+  FE_EINVAL = 1,       /* invalid argument (sizes, null pointers, bad CSR) */
+  FE_ENOMEM = 2,       /* host or device allocation failed */
+  FE_EDEVICE = 3,      /* a HIP runtime call failed; text in fe_last_error() */
+  FE_ENOCONV = 4,      /* solver stopped at max_restarts; outputs hold best estimates */
+  FE_EBREAKDOWN = 5,   /* subspace could not be extended (refill failed) */
+  FE_EUNSUPPORTED = 6  /* valid request this build does not implement */
+} fe_status;
+
+typedef enum { FE_F64 = 0, FE_F32 = 1, FE_BF16 = 2 } fe_dtype;
+
+/* Flags for fe_csr_build / fe_csr_from_csr. */
+#define FE_SYMMETRIZE 0x1u        /* add (v,u) for every (u,v) */
+#define FE_DEDUPE 0x2u            /* merge repeated (u,v) */
+#define FE_DROP_SELF 0x4u         /* drop (u,u) */
+#define FE_RELABEL_BY_DEGREE 0x8u /* renumber vertices by descending degree (ties: lower id first) */
+#define FE_GRAPH_DEFAULT (FE_SYMMETRIZE | FE_DEDUPE | FE_DROP_SELF)
+
+/* Opaque device CSR: int64 row_ptr[n+1], int32 col_idx[nnz], no value array
+   (the adjacency is a 0/1 pattern), plus the degree-binned row schedule and,
+   with FE_RELABEL_BY_DEGREE, the vertex permutation. */
+typedef struct fe_csr fe_csr;
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *fe_last_error(void);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t fe_version(void);
+
+/*
+ * Build the device CSR of a graph from a host edge list (src[e], dst[e]),
+ * 0 <= src, dst < n < 2^31.  Flags select symmetrising, deduplication,
+ * self-loop removal and degree relabelling; each row's columns come out
+ * strictly increasing when FE_DEDUPE is set (non-decreasing otherwise).
+ * The edge arrays are read only during the call.  The sparse matrix format
+ * section of the paper motivates a compact, pattern-only format.
+ * Errors: FE_EINVAL (n <= 0, n_edges < 0, null pointers, ids out of range),
+ * FE_ENOMEM, FE_EDEVICE.  *out is set only on FE_OK; free with fe_csr_free.
+ */
+fe_status fe_csr_build(int64_t n, int64_t n_edges, const int32_t *src, const int32_t *dst,
+                       uint32_t flags, fe_csr **out);
+
+/*
+ * Adopt an existing host CSR (row_ptr[n+1] int64, col_idx[row_ptr[n]] int32),
+ * validated: row_ptr[0] == 0, non-decreasing, columns in [0, n) and strictly
+ * increasing within each row.  Only FE_RELABEL_BY_DEGREE is honoured in flags.
+ * Errors: FE_EINVAL on any violation, FE_ENOMEM, FE_EDEVICE.
+ */
+fe_status fe_csr_from_csr(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                          uint32_t flags, fe_csr **out);
+
+/* Sizes of a handle (any output pointer may be NULL). */
+fe_status fe_csr_info(const fe_csr *A, int64_t *n, int64_t *nnz, int64_t *max_deg);
+
+/*
+ * Host copy of the vertex order used inside the handle: perm[new] = old.
+ * Identity unless built with FE_RELABEL_BY_DEGREE.  fe_spmm works in the
+ * handle's (new) numbering: row `new` of X/Y belongs to vertex perm[new].
+ */
+fe_status fe_csr_perm(const fe_csr *A, int32_t *perm);
+
+/* Host copy of the handle's CSR in its own numbering (row_ptr[n+1], col_idx[nnz]). */
+fe_status fe_csr_export(const fe_csr *A, int64_t *row_ptr, int32_t *col_idx);
+
+void fe_csr_free(fe_csr *A);
+
+/*
+ * Y = A X  (the sparse matrix multiplication section).  X, Y: device, n x b
+ * packed row-major in dtype dt, 1 <= b <= 64, must not overlap.  Row i of Y is
+ * the sum of the rows of X indexed by row i's columns (an empty row gives 0).
+ * Accumulates in FP32 (FP64 for FE_F64); the result is rounded to dt.
+ * Errors: FE_EINVAL (b out of range, null pointers, X/Y overlap), FE_EDEVICE.
+ */
+fe_status fe_spmm(const fe_csr *A, const void *X, void *Y, int32_t b, fe_dtype dt,
+                  void *hip_stream);
+
+/*
+ * C = alpha * V^T W  (MvTransMv).  V: device, nblk >= 1 blocks of n x b, block
+ * j at V + j*blk_stride elements (blk_stride >= n*b); W: device n x b.
+ * C: device FP64, k x b row-major with k = nblk*b.  Arithmetic FP64; the sum
+ * over rows is split into fixed row intervals whose partial k x b matrices
+ * are added in a fixed order (the two-stage reduction), so repeated calls
+ * are bitwise identical.  W may be one of V's blocks.
+ * Allocates a stream-ordered partials buffer (freed stream-ordered).
+ * Errors: FE_EINVAL (n < 1, b not in [1,64], nblk < 1, k > 1024, null), FE_EDEVICE.
+ */
+fe_status fe_gram(const void *V, int32_t nblk, int64_t blk_stride, const void *W, int64_t n,
+                  int32_t b, fe_dtype dt, double alpha, double *C, void *hip_stream);
+
+/*
+ * W = beta * W + alpha * V C  (MvTimesMatAddMv).  W: device n x b; V: nblk
+ * blocks as in fe_gram; C: device FP64 k x b row-major.  FP64 arithmetic,
+ * rounded to dt.  Every output row depends only on the same row of V and W
+ * (row-interval parallelism).  W may equal V only when nblk == 1 and b <= 16
+ * (in-place right multiplication, W <- beta W + alpha W C); any other overlap
+ * is FE_EINVAL.  With beta == 0, W is not read (NaNs in it do not propagate).
+ * Errors: FE_EINVAL, FE_EDEVICE.
+ */
+fe_status fe_block_update(void *W, int64_t n, int32_t b, const void *V, int32_t nblk,
+                          int64_t blk_stride, const double *C, double alpha, double beta,
+                          fe_dtype dt, void *hip_stream);
+
+/* Options of fe_krylov_schur.  Zero-initialise, then set what you need. */
+typedef struct {
+  fe_dtype dt;           /* storage dtype of the subspace (default FE_F64 = 0) */
+  int32_t which;         /* 0 = largest magnitude (only mode) */
+  int32_t max_restarts;  /* 0 -> 500 */
+  uint64_t seed;         /* random start and refill draws */
+  const void *start;     /* device n x block start block in dt, original vertex
+                            order; NULL = N(0,1) drawn from `seed` */
+  void *hip_stream;      /* stream for all work (NULL = null stream) */
+  double eta;            /* dependence threshold; 0 -> 1e-6 (F64), 1e-5 (F32), 3e-2 (BF16) */
+  int32_t profile;       /* 1 = time each kernel class with HIP events */
+  int32_t verbose;       /* 1 = print one line per restart to stderr */
+} fe_ks_opts;
+
+/* Per-solve report (all times in seconds). */
+typedef struct {
+  int32_t restarts;        /* restarts performed */
+  int32_t spmm_calls;      /* width-`block` products in the iteration */
+  int32_t spmm_cols;       /* columns multiplied, including the final check */
+  int32_t converged;       /* number of wanted pairs meeting tol at the last check */
+  int32_t refills;         /* dependent columns replaced by random vectors */
+  int32_t gram_calls, update_calls;
+  double rho[64];          /* Krylov-Schur residual estimate / max(eps^(2/3),|theta|) per pair */
+  double ritz[64];         /* Ritz values of the projected matrix at the last check */
+  double resid[64];        /* explicit ||A x - q x|| / (max(eps^(2/3),|q|) ||x||), q the
+                              FP64 Rayleigh quotient returned in evals */
+  double t_spmm, t_gram, t_update, t_other_dev; /* event-timed kernel time (profile=1);
+                              t_spmm covers the width-`block` products only */
+  double bytes_spmm, bytes_gram, bytes_update;   /* algorithmic HBM bytes moved by those
+                              kernel classes: SpMM 4 nnz + 8 (n+1) + 2 n b s; Gram n k s;
+                              update n b s (k/b + 2) (s = element size) */
+  double t_host, t_total;  /* host small-matrix work; wall clock of the solve */
+} fe_ks_report;
+
+/*
+ * Block Krylov-Schur for the nev largest-magnitude eigenpairs of the
+ * symmetric pattern matrix A (the paper's selected solver, following its
+ * generic eigen-iteration with the block extension).  block = b vectors per
+ * step, m = subspace size (m % block == 0, 1 <= nev <= m - block, m <= 128,
+ * block <= 16, m + block <= n), tol > 0: pair i is converged when its
+ * Krylov-Schur residual estimate is <= tol * max(eps^(2/3), |theta_i|), eps
+ * the FP64 unit roundoff.
+ * Final check (FP64 whatever the storage dtype): the Ritz vectors X = V Y are
+ * formed in FP64, multiplied by A in FP64, and each value returned is the
+ * Rayleigh quotient x^T A x / x^T x with its explicit residual.
+ * Outputs: evals (host double[nev], pairs ordered by Ritz value |theta|
+ * descending, ties to the larger theta); evecs (device n x nev in opts->dt,
+ * original vertex order, 2-norm 1 up to storage rounding) or NULL; rep (host)
+ * or NULL.
+ * Workspace: (m + block) * n elements of dt, 2 * nev * n doubles and small
+ * FP64 buffers, allocated for the call and freed before return.  Synchronises the
+ * stream before returning.
+ * Errors: FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_ENOCONV (max_restarts reached;
+ * outputs hold the current estimates), FE_EUNSUPPORTED (sizes beyond the limits).
+ */
+fe_status fe_krylov_schur(const fe_csr *A, int32_t nev, int32_t block, int32_t m, double tol,
+                          const fe_ks_opts *opts, double *evals, void *evecs,
+                          fe_ks_report *rep);
+
+/*
+ * Host utility: eigendecomposition of a small dense symmetric matrix (the
+ * projected problem of the eigen-iteration, which the paper solves with
+ * LAPACK-class code).  a: host n x n row-major (read only); w: host n
+ * eigenvalues, unordered; z: host n x n row-major, column j the unit
+ * eigenvector of w[j].  Householder tridiagonalisation + implicit-shift QL.
+ * Errors: FE_EINVAL (n < 1, NULL), FE_ENOCONV (QL iteration limit).
+ */
+fe_status fe_dense_symeig(int32_t n, const double *a, double *w, double *z);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FE_H */

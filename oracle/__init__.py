@@ -59,7 +59,8 @@ def ptr(a: np.ndarray):
 
 
 from .csr import csr_from_edges, degrees  # noqa: E402
-from .ops import spmm, gram, block_update, col_norms, max_threads  # noqa: E402
+from .ops import (spmm, gram, block_update, col_norms, max_threads, round_bf16,  # noqa: E402
+                  spmm_rows_from_edges)
 from .dense_eig import jacobi_eigh  # noqa: E402
 from .rng import philox4x32_10, refill_column  # noqa: E402
 from .krylov_schur import krylov_schur, KSResult, restart_keep, ritz_scale, EPS23  # noqa: E402

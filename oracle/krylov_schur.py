@@ -148,7 +148,7 @@ def _ritz_order(theta: np.ndarray) -> np.ndarray:
 
 
 def krylov_schur(spmm, n: int, nev: int, b: int, m: int, tol: float, X0: np.ndarray,
-                 max_restarts: int = 500, seed: int = 0, eta: float = 1e-10) -> KSResult:
+                 max_restarts: int = 500, seed: int = 0, eta: float = 1e-6) -> KSResult:
     """spmm(X) must return A @ X for an (n, cols) float64 array."""
     if m % b or nev > m - b or nev < 1 or tol <= 0 or m + b > n:
         raise ValueError("need m % b == 0, 1 <= nev <= m - b, tol > 0, m + b <= n")

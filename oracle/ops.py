@@ -46,3 +46,35 @@ def block_update(W: np.ndarray, V: np.ndarray, C: np.ndarray, alpha: float = 1.0
 
 def col_norms(X: np.ndarray) -> np.ndarray:
     return np.sqrt(np.sum(X * X, axis=0))
+
+
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Round to bfloat16 (round to nearest, ties to even, on the FP32 bit
+    pattern: add 0x7FFF plus the lowest kept bit, clear the low 16 bits).
+    Exact for inputs that are exactly representable in FP32."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    out = u.astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(np.isfinite(f), out, f.astype(np.float64))
+
+
+def spmm_rows_from_edges(n: int, src: np.ndarray, dst: np.ndarray, X: np.ndarray,
+                         rows: np.ndarray) -> np.ndarray:
+    """Rows `rows` (sorted, distinct) of A X, with A the symmetrised,
+    deduplicated, loop-free pattern of the edge stream, without building A.
+    Each row sums its neighbours' X rows in ascending neighbour order."""
+    rows = np.asarray(rows, dtype=np.int64)
+    s = np.asarray(src, dtype=np.int64)
+    d = np.asarray(dst, dtype=np.int64)
+    m1 = np.isin(s, rows)
+    m2 = np.isin(d, rows)
+    u = np.concatenate([s[m1], d[m2]])
+    v = np.concatenate([d[m1], s[m2]])
+    keep = u != v
+    key = np.unique(u[keep] * np.int64(n) + v[keep])
+    ru = key // n
+    cv = key - ru * n
+    Y = np.zeros((rows.shape[0], X.shape[1]))
+    np.add.at(Y, np.searchsorted(rows, ru), np.asarray(X, dtype=np.float64)[cv])
+    return Y

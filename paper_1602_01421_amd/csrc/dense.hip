@@ -1,0 +1,576 @@
+// Tall-and-skinny subspace kernels (the vector-subspace section's table of
+// dense operations and its subsection on parallelising them).
+//
+//   gram    C = alpha V^T W          (MvTransMv)       -- FP64 MFMA, two stages
+//   update  W = beta W + alpha V C   (MvTimesMatAddMv) -- FP64 FMA per row
+//   rotate  V[:, :p] = V[:, :m] Y    (restart: Ritz vectors in place)
+//   combine Out = V Y                (final Ritz vectors)
+//   resid   ||A x_i - theta_i x_i||^2 and ||x_i||^2 per column (MvNorm/MvAddMv/MvScale2 fused)
+//   permute, copy, random fill
+//
+// A subspace of k columns is a list of k/b blocks, each n x b row-major
+// (packed); row r of every block is contiguous, so a row interval of all
+// blocks is read with coalesced vector loads.  Outputs that are small
+// matrices are reduced in two stages: per-workgroup partials over a fixed
+// row interval, then a fixed-order sum (deterministic), as the paper
+// describes for non-tall-and-skinny outputs.
+#include "dev_common.h"
+#include "fe_internal.h"
+
+namespace fe {
+namespace {
+
+// ----------------------------------------------------------------- Gram
+// v_mfma_f64_4x4x4f64 computes four independent 4x4x4 products per
+// wavefront.  Operand layout (measured on gfx950): lane = 16*kk + 4*blk + x,
+// where kk is the contraction index, blk the block, and x the output row i
+// for A or the output column j for B.  The accumulator of lane
+// 16*i + 4*blk + j holds D_blk[i][j].
+// Mapping: contraction index = one of four consecutive matrix rows; block
+// blk = a group of four V columns; the same four W columns feed all blocks.
+// One instruction therefore performs 4 rows x 16 V-columns x 4 W-columns.
+constexpr int kGramWG = 512;          // 8 wavefronts
+constexpr int kGramRowsPerIter = 16;  // rows per wavefront per iteration (4 MFMA steps)
+constexpr int kGramPG = 4;            // 16-column V groups per workgroup (64 V columns)
+
+template <typename T, int NQG>
+__global__ __launch_bounds__(kGramWG) void gram_kernel(const T* __restrict__ V, int64_t stride,
+                                                       const T* __restrict__ W, int64_t n,
+                                                       int32_t b, int32_t k, int64_t rows_per_wg,
+                                                       double* __restrict__ partials) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kk = lane >> 4, blk = (lane >> 2) & 3, x = lane & 3;
+  const int p_base = blockIdx.y * (16 * kGramPG);
+  const int q_base = blockIdx.z * (4 * NQG);
+  const int npg = min(kGramPG, (k - p_base + 15) / 16);
+  const int nqg = min(NQG, (b - q_base + 3) / 4);
+  int64_t aoff[kGramPG];
+  bool aval[kGramPG];
+#pragma unroll
+  for (int pg = 0; pg < kGramPG; ++pg) {
+    const int p = p_base + pg * 16 + 4 * blk + x;
+    aval[pg] = p < k;
+    aoff[pg] = aval[pg] ? (int64_t)(p / b) * stride + (p % b) : 0;
+  }
+  int boff[NQG];
+  bool bval[NQG];
+#pragma unroll
+  for (int qg = 0; qg < NQG; ++qg) {
+    const int q = q_base + qg * 4 + x;
+    bval[qg] = q < b;
+    boff[qg] = bval[qg] ? q : 0;
+  }
+  double acc[kGramPG][NQG];
+#pragma unroll
+  for (int pg = 0; pg < kGramPG; ++pg)
+#pragma unroll
+    for (int qg = 0; qg < NQG; ++qg) acc[pg][qg] = 0.0;
+
+  const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r_end = min(n, r_begin + rows_per_wg);
+  for (int64_t r0 = r_begin + wave * kGramRowsPerIter; r0 < r_end;
+       r0 += (kGramWG / 64) * kGramRowsPerIter) {
+    double a[4][kGramPG], bb[4][NQG];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t row = r0 + 4 * u + kk;
+      const bool rv = row < r_end;
+      const int64_t rb = row * b;
+#pragma unroll
+      for (int pg = 0; pg < kGramPG; ++pg)
+        a[u][pg] = (rv && aval[pg]) ? load_f64(V + aoff[pg] + rb) : 0.0;
+#pragma unroll
+      for (int qg = 0; qg < NQG; ++qg)
+        bb[u][qg] = (rv && bval[qg]) ? load_f64(W + rb + boff[qg]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int pg = 0; pg < kGramPG; ++pg)
+        if (pg < npg)
+#pragma unroll
+          for (int qg = 0; qg < NQG; ++qg)
+            if (qg < nqg)
+              acc[pg][qg] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u][pg], bb[u][qg], acc[pg][qg],
+                                                               0, 0, 0);
+  }
+  // wavefront partials added in wavefront order (deterministic)
+  __shared__ double red[kGramPG][NQG][64];
+  for (int w = 0; w < kGramWG / 64; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int pg = 0; pg < kGramPG; ++pg)
+#pragma unroll
+        for (int qg = 0; qg < NQG; ++qg)
+          red[pg][qg][lane] = (w == 0 ? 0.0 : red[pg][qg][lane]) + acc[pg][qg];
+    }
+    __syncthreads();
+  }
+  double* out = partials + (int64_t)blockIdx.x * k * b;
+  for (int idx = threadIdx.x; idx < kGramPG * NQG * 64; idx += kGramWG) {
+    const int l = idx & 63, qg = (idx >> 6) % NQG, pg = (idx >> 6) / NQG;
+    const int i = l >> 4, bl = (l >> 2) & 3, j = l & 3;
+    const int p = p_base + pg * 16 + 4 * bl + i, q = q_base + qg * 4 + j;
+    if (p < k && q < b) out[(int64_t)p * b + q] = red[pg][qg][l];
+  }
+}
+
+// C[e] = alpha * sum over partial sets x (fixed order: strided lanes, then group order)
+__global__ __launch_bounds__(1024) void reduce_partials(const double* __restrict__ partials,
+                                                        int32_t nsets, int32_t len, double alpha,
+                                                        double* __restrict__ out) {
+  const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + l;
+  double s = 0.0;
+  if (e < len)
+    for (int x = g; x < nsets; x += 16) s += partials[(int64_t)x * len + e];
+  __shared__ double red[16][64];
+  red[g][l] = s;
+  __syncthreads();
+  if (g == 0 && e < len) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t += red[i][l];
+    out[e] = alpha * t;
+  }
+}
+
+int gram_sets(int64_t n) {
+  // ~2 workgroups of 8 wavefronts per CU; never fewer rows than one iteration
+  int64_t by_rows = (n + 8 * kGramRowsPerIter - 1) / (8 * kGramRowsPerIter);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(512, by_rows));
+}
+
+template <typename T>
+fe_status gram_t(const void* V, int32_t nblk, int64_t stride, const void* W, int64_t n, int32_t b,
+                 double alpha, double* C, double* partials, hipStream_t s) {
+  const int32_t k = nblk * b;
+  const int gx = gram_sets(n);
+  int64_t rows_per_wg = (n + gx - 1) / gx;
+  rows_per_wg = (rows_per_wg + 15) / 16 * 16;
+  const int gy = (k + 16 * kGramPG - 1) / (16 * kGramPG);
+  const int gz = (b + 15) / 16;
+  dim3 grid(gx, gy, gz);
+  const T* Vp = static_cast<const T*>(V);
+  const T* Wp = static_cast<const T*>(W);
+  if (b <= 4)
+    hipLaunchKernelGGL((gram_kernel<T, 1>), grid, dim3(kGramWG), 0, s, Vp, stride, Wp, n, b, k,
+                       rows_per_wg, partials);
+  else if (b <= 8)
+    hipLaunchKernelGGL((gram_kernel<T, 2>), grid, dim3(kGramWG), 0, s, Vp, stride, Wp, n, b, k,
+                       rows_per_wg, partials);
+  else
+    hipLaunchKernelGGL((gram_kernel<T, 4>), grid, dim3(kGramWG), 0, s, Vp, stride, Wp, n, b, k,
+                       rows_per_wg, partials);
+  FE_HIP(hipGetLastError());
+  const int len = k * b;
+  hipLaunchKernelGGL(reduce_partials, dim3((len + 63) / 64), dim3(1024), 0, s, partials, gx, len,
+                     alpha, C);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+// ---------------------------------------------------------------- update
+// One thread per row; C (k x B, pre-scaled by alpha) is staged in LDS and read
+// with wavefront-uniform addresses (broadcast).
+template <typename T, int B>
+__global__ __launch_bounds__(256) void update_kernel(T* W, int64_t n,
+                                                     const T* V, int32_t nblk,
+                                                     int64_t stride, const double* __restrict__ C,
+                                                     double alpha, double beta) {
+  extern __shared__ double Cs[];
+  const int k = nblk * B;
+  for (int i = threadIdx.x; i < k * B; i += blockDim.x) Cs[i] = alpha * C[i];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  constexpr int VEC = (B * sizeof(T) >= 16) ? 16 / sizeof(T) : B;
+  double acc[B];
+#pragma unroll
+  for (int q = 0; q < B; ++q) acc[q] = 0.0;
+  for (int jb = 0; jb < nblk; ++jb) {
+    const T* vp = V + jb * stride + r * B;
+    double v[B];
+#pragma unroll
+    for (int c0 = 0; c0 < B; c0 += VEC) {
+      double tmp[VEC];
+      load_vec<T, VEC>(vp + c0, tmp);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) v[c0 + c] = tmp[c];
+    }
+    const double* cr = Cs + jb * B * B;
+#pragma unroll
+    for (int c = 0; c < B; ++c)
+#pragma unroll
+      for (int q = 0; q < B; ++q) acc[q] = fma(v[c], cr[c * B + q], acc[q]);
+  }
+  T* wp = W + r * B;
+  if (beta != 0.0) {
+#pragma unroll
+    for (int c0 = 0; c0 < B; c0 += VEC) {
+      double tmp[VEC];
+      load_vec<T, VEC>(wp + c0, tmp);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) acc[c0 + c] = fma(beta, tmp[c], acc[c0 + c]);
+    }
+  }
+#pragma unroll
+  for (int c0 = 0; c0 < B; c0 += VEC) store_vec<T, VEC>(wp + c0, acc + c0);
+}
+
+// Any b: one thread per output element.
+template <typename T>
+__global__ __launch_bounds__(256) void update_generic(T* __restrict__ W, int64_t n, int32_t b,
+                                                      const T* __restrict__ V, int32_t nblk,
+                                                      int64_t stride, const double* __restrict__ C,
+                                                      double alpha, double beta) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * b) return;
+  const int64_t r = e / b;
+  const int q = (int)(e % b);
+  double acc = 0.0;
+  for (int jb = 0; jb < nblk; ++jb)
+    for (int c = 0; c < b; ++c)
+      acc = fma(load_f64(V + jb * stride + r * b + c), C[(int64_t)(jb * b + c) * b + q], acc);
+  acc *= alpha;
+  if (beta != 0.0) acc = fma(beta, load_f64(W + e), acc);
+  W[e] = to_storage<T, double>(acc);
+}
+
+template <typename T>
+fe_status update_t(void* W, int64_t n, int32_t b, const void* V, int32_t nblk, int64_t stride,
+                   const double* C, double alpha, double beta, hipStream_t s) {
+  T* Wp = static_cast<T*>(W);
+  const T* Vp = static_cast<const T*>(V);
+  const int64_t g = (n + 255) / 256;
+  const size_t lds = (size_t)nblk * b * b * sizeof(double);
+  if (g > 0x7FFFFFFF) return fail(FE_EUNSUPPORTED, "update: n too large");
+#define FE_UPD(BB)                                                                          \
+  case BB:                                                                                  \
+    hipLaunchKernelGGL((update_kernel<T, BB>), dim3((uint32_t)g), dim3(256), lds, s, Wp, n, Vp, \
+                       nblk, stride, C, alpha, beta);                                      \
+    break;
+  if (lds <= 64 * 1024 && (b == 1 || b == 2 || b == 4 || b == 8 || b == 16)) {
+    switch (b) { FE_UPD(1) FE_UPD(2) FE_UPD(4) FE_UPD(8) FE_UPD(16) }
+  } else {
+    const int64_t ge = (n * b + 255) / 256;
+    if (ge > 0x7FFFFFFF) return fail(FE_EUNSUPPORTED, "update: n*b too large");
+    hipLaunchKernelGGL((update_generic<T>), dim3((uint32_t)ge), dim3(256), 0, s, Wp, n, b, Vp, nblk,
+                       stride, C, alpha, beta);
+  }
+#undef FE_UPD
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+// ------------------------------------------------------- rotate / combine
+// Out row r = (V row r) * Y, Y is m x p (FP64, LDS).  All of a row's inputs
+// are read before any of its outputs is written, so the in-place form
+// (Out = the first p/b blocks of V) is safe row by row.
+constexpr int kRotMax = 64;
+
+template <typename T, typename TO, int B>
+__global__ __launch_bounds__(256) void rotate_kernel(TO* Out, int32_t out_mode,
+                                                     int32_t c_out, int64_t n, const T* V,
+                                                     int32_t nblk, int64_t stride,
+                                                     const double* __restrict__ Y, int32_t p) {
+  extern __shared__ double Ys[];
+  const int m = nblk * B;
+  for (int i = threadIdx.x; i < m * p; i += blockDim.x) Ys[i] = Y[i];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  constexpr int VEC = (B * sizeof(T) >= 16) ? 16 / sizeof(T) : B;
+  double acc[kRotMax];
+#pragma unroll
+  for (int o = 0; o < kRotMax; ++o) acc[o] = 0.0;
+  for (int jb = 0; jb < nblk; ++jb) {
+    const T* vp = V + jb * stride + r * B;
+#pragma unroll
+    for (int c0 = 0; c0 < B; c0 += VEC) {
+      double tmp[VEC];
+      load_vec<T, VEC>(vp + c0, tmp);
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) {
+        const double* yr = Ys + (jb * B + c0 + c) * p;
+#pragma unroll
+        for (int o = 0; o < kRotMax; ++o)
+          if (o < p) acc[o] = fma(tmp[c], yr[o], acc[o]);
+      }
+    }
+  }
+  if constexpr (sizeof(TO) == sizeof(T)) {
+    if (out_mode == 0) {  // back into the first p/B blocks of V
+#pragma unroll
+      for (int ob = 0; ob < kRotMax / B; ++ob)
+        if (ob * B < p) {
+#pragma unroll
+          for (int c0 = 0; c0 < B; c0 += VEC)
+            store_vec<TO, VEC>(Out + ob * stride + r * B + c0, acc + ob * B + c0);
+        }
+      return;
+    }
+  }
+  // packed n x c_out
+#pragma unroll
+  for (int o = 0; o < kRotMax; ++o)
+    if (o < c_out) Out[r * c_out + o] = to_storage<TO, double>(acc[o]);
+}
+
+template <typename T, typename TO = T>
+fe_status rotate_t(void* Out, int32_t out_mode, int32_t c_out, int64_t n, int32_t b,
+                   const void* V, int32_t nblk, int64_t stride, const double* Y, int32_t p,
+                   hipStream_t s) {
+  const int64_t g = (n + 255) / 256;
+  const size_t lds = (size_t)nblk * b * p * sizeof(double);
+  if (p > kRotMax || lds > 64 * 1024)
+    return fail(FE_EUNSUPPORTED, "rotate: p=%d (max %d) or m*p too large", p, kRotMax);
+  TO* O = static_cast<TO*>(Out);
+  const T* Vp = static_cast<const T*>(V);
+#define FE_ROT(BB)                                                                                \
+  case BB:                                                                                        \
+    hipLaunchKernelGGL((rotate_kernel<T, TO, BB>), dim3((uint32_t)g), dim3(256), lds, s, O, out_mode, \
+                       c_out, n, Vp, nblk, stride, Y, p);                                        \
+    break;
+  switch (b) {
+    FE_ROT(1) FE_ROT(2) FE_ROT(4) FE_ROT(8) FE_ROT(16)
+    default:
+      return fail(FE_EUNSUPPORTED, "rotate: block %d not in {1,2,4,8,16}", b);
+  }
+#undef FE_ROT
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+// -------------------------------------------------------------- residual
+// Per workgroup, for each column i < c of the FP64 blocks X and AX (n x c):
+// sums of x*ax, x*x and (ax - theta_i x)^2; partials reduced later.
+constexpr int kResCols = 64;
+__global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ AX,
+                                                    const double* __restrict__ X, int64_t n,
+                                                    int32_t c, const double* __restrict__ theta,
+                                                    int64_t rows_per_wg,
+                                                    double* __restrict__ partials) {
+  __shared__ double red[4][3 * kResCols];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r1 = min(n, r0 + rows_per_wg);
+  for (int i0 = 0; i0 < c; i0 += 8) {
+    double s0[8], s1[8], s2[8], th[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      s0[u] = s1[u] = s2[u] = 0.0;
+      th[u] = (i0 + u < c) ? theta[i0 + u] : 0.0;
+    }
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u < c) {
+          const double x = X[r * c + i0 + u], ax = AX[r * c + i0 + u];
+          const double d = ax - th[u] * x;
+          s0[u] = fma(x, ax, s0[u]);
+          s1[u] = fma(x, x, s1[u]);
+          s2[u] = fma(d, d, s2[u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        s0[u] += __shfl_xor(s0[u], off, 64);
+        s1[u] += __shfl_xor(s1[u], off, 64);
+        s2[u] += __shfl_xor(s2[u], off, 64);
+      }
+    if (lane == 0)
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u < c) {
+          red[wave][3 * (i0 + u)] = s0[u];
+          red[wave][3 * (i0 + u) + 1] = s1[u];
+          red[wave][3 * (i0 + u) + 2] = s2[u];
+        }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 3 * c; e += 256)
+    partials[(int64_t)blockIdx.x * 3 * c + e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+}
+
+int resid_sets(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 1023) / 1024));
+}
+
+// FP64 rows -> storage dtype, optionally scattered through perm (dst[perm[r]] = src[r])
+template <typename T>
+__global__ void store_rows_kernel(T* __restrict__ dst, const double* __restrict__ src,
+                                  const int32_t* __restrict__ perm, int64_t n, int32_t c) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * c) return;
+  const int64_t r = e / c, j = e % c;
+  const int64_t o = perm ? (int64_t)perm[r] : r;
+  dst[o * c + j] = to_storage<T, double>(src[e]);
+}
+
+// ------------------------------------------------------------- permute/rng
+template <typename T>
+__global__ void permute_kernel(T* __restrict__ dst, const T* __restrict__ src,
+                               const int32_t* __restrict__ perm, int64_t n, int32_t c,
+                               int32_t scatter) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * c) return;
+  const int64_t r = e / c, j = e % c;
+  const int64_t o = perm[r];
+  if (scatter)
+    dst[o * c + j] = src[e];
+  else
+    dst[e] = src[o * c + j];
+}
+
+template <typename T>
+__global__ void random_kernel(T* __restrict__ W, int64_t n, int32_t b, uint32_t mask, int32_t mode,
+                              uint32_t k0, uint32_t k1, uint32_t step,
+                              const int32_t* __restrict__ perm) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * b) return;
+  const int64_t r = e / b;
+  const int j = (int)(e % b);
+  if (!((mask >> j) & 1u)) return;
+  const uint64_t i = perm ? (uint64_t)(uint32_t)perm[r] : (uint64_t)r;
+  double v;
+  if (mode == 1) {  // refill: uniform [-1, 1), exact in FP32
+    uint4 w = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)(i >> 32), step, 0x52460000u + j),
+                            k0, k1);
+    v = (double)(w.x >> 8) * (1.0 / 8388608.0) - 1.0;
+  } else {  // start block: N(0,1) by Box-Muller
+    uint4 w = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)(i >> 32), j, 0x53545254u), k0, k1);
+    const double u1 = 1.0 - ((double)(w.x >> 5) * 67108864.0 + (double)(w.y >> 6)) *
+                                (1.0 / 9007199254740992.0);
+    const double u2 = ((double)(w.z >> 5) * 67108864.0 + (double)(w.w >> 6)) *
+                      (1.0 / 9007199254740992.0);
+    v = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  }
+  W[e] = to_storage<T, double>(v);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers
+size_t gram_partials_doubles(int64_t n, int32_t k, int32_t b) {
+  return (size_t)gram_sets(n) * (size_t)k * (size_t)b;
+}
+
+fe_status gram_launch(const void* V, int32_t nblk, int64_t stride, const void* W, int64_t n,
+                      int32_t b, fe_dtype dt, double alpha, double* C, double* partials,
+                      hipStream_t s) {
+  switch (dt) {
+    case FE_F64: return gram_t<double>(V, nblk, stride, W, n, b, alpha, C, partials, s);
+    case FE_F32: return gram_t<float>(V, nblk, stride, W, n, b, alpha, C, partials, s);
+    case FE_BF16: return gram_t<bf16_t>(V, nblk, stride, W, n, b, alpha, C, partials, s);
+  }
+  return fail(FE_EINVAL, "gram: bad dtype");
+}
+
+fe_status update_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk, int64_t stride,
+                        const double* C, double alpha, double beta, fe_dtype dt, hipStream_t s) {
+  switch (dt) {
+    case FE_F64: return update_t<double>(W, n, b, V, nblk, stride, C, alpha, beta, s);
+    case FE_F32: return update_t<float>(W, n, b, V, nblk, stride, C, alpha, beta, s);
+    case FE_BF16: return update_t<bf16_t>(W, n, b, V, nblk, stride, C, alpha, beta, s);
+  }
+  return fail(FE_EINVAL, "update: bad dtype");
+}
+
+fe_status rotate_launch(void* V, int64_t n, int32_t b, int32_t nblk_in, int32_t nblk_out,
+                        int64_t stride, const double* Y, fe_dtype dt, hipStream_t s) {
+  const int32_t p = nblk_out * b;
+  switch (dt) {
+    case FE_F64: return rotate_t<double>(V, 0, 0, n, b, V, nblk_in, stride, Y, p, s);
+    case FE_F32: return rotate_t<float>(V, 0, 0, n, b, V, nblk_in, stride, Y, p, s);
+    case FE_BF16: return rotate_t<bf16_t>(V, 0, 0, n, b, V, nblk_in, stride, Y, p, s);
+  }
+  return fail(FE_EINVAL, "rotate: bad dtype");
+}
+
+fe_status combine_launch(double* Out, int32_t c, int64_t n, int32_t b, const void* V, int32_t nblk,
+                         int64_t stride, const double* Y, fe_dtype dt, hipStream_t s) {
+  switch (dt) {
+    case FE_F64: return rotate_t<double, double>(Out, 1, c, n, b, V, nblk, stride, Y, c, s);
+    case FE_F32: return rotate_t<float, double>(Out, 1, c, n, b, V, nblk, stride, Y, c, s);
+    case FE_BF16: return rotate_t<bf16_t, double>(Out, 1, c, n, b, V, nblk, stride, Y, c, s);
+  }
+  return fail(FE_EINVAL, "combine: bad dtype");
+}
+
+size_t resid_partials_doubles(int64_t n, int32_t c) { return (size_t)resid_sets(n) * 3 * c; }
+
+fe_status resid_launch(const double* AX, const double* X, int64_t n, int32_t c,
+                       const double* theta, double* sums, double* partials, hipStream_t s) {
+  if (c > kResCols) return fail(FE_EUNSUPPORTED, "resid: %d columns (max %d)", c, kResCols);
+  const int g = resid_sets(n);
+  const int64_t rpw = (n + g - 1) / g;
+  hipLaunchKernelGGL(resid_kernel, dim3(g), dim3(256), 0, s, AX, X, n, c, theta, rpw, partials);
+  FE_HIP(hipGetLastError());
+  hipLaunchKernelGGL(reduce_partials, dim3((3 * c + 63) / 64), dim3(1024), 0, s, partials, g,
+                     3 * c, 1.0, sums);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status store_rows(void* dst, const double* src, const int32_t* perm, int64_t n, int32_t c,
+                     fe_dtype dt, hipStream_t s) {
+  const int64_t g = (n * c + 255) / 256;
+  if (g > 0x7FFFFFFF) return fail(FE_EUNSUPPORTED, "store_rows: too large");
+#define FE_ST(TT)                                                                                 \
+  hipLaunchKernelGGL((store_rows_kernel<TT>), dim3((uint32_t)g), dim3(256), 0, s, static_cast<TT*>(dst), \
+                     src, perm, n, c);
+  switch (dt) {
+    case FE_F64: FE_ST(double) break;
+    case FE_F32: FE_ST(float) break;
+    case FE_BF16: FE_ST(bf16_t) break;
+  }
+#undef FE_ST
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status copy_block(void* dst, const void* src, int64_t n, int32_t b, fe_dtype dt,
+                     hipStream_t s) {
+  FE_HIP(hipMemcpyAsync(dst, src, (size_t)n * b * dtype_size(dt), hipMemcpyDeviceToDevice, s));
+  return FE_OK;
+}
+
+fe_status permute_rows(void* dst, const void* src, const int32_t* perm, int64_t n, int32_t c,
+                       fe_dtype dt, bool scatter, hipStream_t s) {
+  const int64_t g = (n * c + 255) / 256;
+  if (g > 0x7FFFFFFF) return fail(FE_EUNSUPPORTED, "permute: too large");
+#define FE_PERM(TT)                                                                              \
+  hipLaunchKernelGGL((permute_kernel<TT>), dim3((uint32_t)g), dim3(256), 0, s, static_cast<TT*>(dst), \
+                     static_cast<const TT*>(src), perm, n, c, (int32_t)scatter);
+  switch (dt) {
+    case FE_F64: FE_PERM(double) break;
+    case FE_F32: FE_PERM(float) break;
+    case FE_BF16: FE_PERM(bf16_t) break;
+  }
+#undef FE_PERM
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status random_fill(void* W, int64_t n, int32_t b, uint32_t mask, int32_t mode, uint64_t seed,
+                      uint32_t step, const int32_t* perm, fe_dtype dt, hipStream_t s) {
+  const int64_t g = (n * b + 255) / 256;
+  if (g > 0x7FFFFFFF) return fail(FE_EUNSUPPORTED, "random_fill: too large");
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#define FE_RNG(TT)                                                                               \
+  hipLaunchKernelGGL((random_kernel<TT>), dim3((uint32_t)g), dim3(256), 0, s, static_cast<TT*>(W), n, \
+                     b, mask, mode, k0, k1, step, perm);
+  switch (dt) {
+    case FE_F64: FE_RNG(double) break;
+    case FE_F32: FE_RNG(float) break;
+    case FE_BF16: FE_RNG(bf16_t) break;
+  }
+#undef FE_RNG
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+}  // namespace fe

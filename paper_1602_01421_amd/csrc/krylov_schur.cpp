@@ -1,0 +1,570 @@
+// Block Krylov-Schur driver (host control loop, device subspace).
+//
+// The paper's eigensolver is Anasazi's block Krylov-Schur, following its
+// generic eigen-iteration: (1) update the subspace (sparse product plus
+// reorthogonalisation), (2) solve the projected m x m problem, (3) Ritz
+// pairs and residuals, (4) convergence test; with the block extension b
+// vectors enter per step and the subspace holds m = b * NB vectors.  This is
+// Stewart's Krylov-Schur for symmetric A (block thick-restart Lanczos with
+// full reorthogonalisation):
+//
+//   state   A V = V T + Q B,  V n x k orthonormal, Q n x b orthonormal, Q _|_ V
+//   expand  V <- [V Q]; W = A Q; C = CGS2(V, W); W = Q' R; T gets C; B = [0 R]
+//   check   S = sym(T) = Y diag(theta) Y^T, |theta| descending; rho_i = ||B y_i||
+//   restart V[:, :p] <- V Y[:, :p], T <- diag(theta_1..p), B <- B Y[:, :p]
+//
+// Device memory holds the whole subspace: m/b + 1 packed n x b blocks.  The
+// block after the last basis block holds W, which becomes the next Q in
+// place, so a Gram product over k/b + 1 blocks returns both V^T W and W^T W.
+// Only small FP64 matrices (<= (m+b) x b, m x m) cross to the host.
+//
+// Readings where the paper is silent: dependence threshold eta (a column is
+// dependent when its norm after projection against V and the earlier
+// accepted columns is <= eta times its norm before projection; the test is
+// taken on the Gram matrix, whose cancellation resolves ratios down to about
+// sqrt(FP64 unit roundoff) = 1.5e-8, so eta >= 1e-6); dependent
+// columns are refilled with Philox uniform [-1, 1) draws orthogonalised
+// against everything accepted; kept Ritz vectors p = m - b*max(1,
+// floor((m-nev)/(2b))); convergence rho_i <= tol * max(eps^(2/3), |theta_i|)
+// with eps the FP64 unit roundoff (ARPACK's convention).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "fe_internal.h"
+
+namespace fe {
+namespace {
+
+using clk = std::chrono::steady_clock;
+// Denominator of the convergence test: max(eps^(2/3), |theta|), eps = 2^-52.
+static double ritz_scale(double theta) {
+  return std::max(std::fabs(theta), std::cbrt(2.220446049250313e-16 * 2.220446049250313e-16));
+}
+
+static double secs(clk::time_point a, clk::time_point b) {
+  return std::chrono::duration<double>(b - a).count();
+}
+
+enum ProfCls { P_SPMM = 0, P_GRAM = 1, P_UPDATE = 2, P_OTHER = 3 };
+
+struct Prof {
+  bool on = false;
+  hipStream_t s = nullptr;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  double t[4] = {0, 0, 0, 0};
+  int open_cls = -1;
+  hipEvent_t open_a = nullptr;
+  void begin(int cls) {
+    if (!on) return;
+    hipEventCreate(&open_a);
+    hipEventRecord(open_a, s);
+    open_cls = cls;
+  }
+  void end() {
+    if (!on || open_cls < 0) return;
+    hipEvent_t e;
+    hipEventCreate(&e);
+    hipEventRecord(e, s);
+    recs.push_back({open_cls, open_a, e});
+    open_cls = -1;
+  }
+  void flush() {  // stream must be synchronised
+    for (auto& r : recs) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, r.a, r.b);
+      t[r.cls] += ms * 1e-3;
+      hipEventDestroy(r.a);
+      hipEventDestroy(r.b);
+    }
+    recs.clear();
+  }
+  ~Prof() { flush(); }
+};
+
+struct DevBuf {
+  std::vector<void*> ptrs;
+  ~DevBuf() {
+    for (void* p : ptrs) hipFree(p);
+  }
+  fe_status get(void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
+    if (e != hipSuccess)
+      return fail(FE_ENOMEM, "fe_krylov_schur: hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    ptrs.push_back(*p);
+    return FE_OK;
+  }
+};
+
+struct HostBuf {
+  std::vector<void*> ptrs;
+  ~HostBuf() {
+    for (void* p : ptrs) hipHostFree(p);
+  }
+  fe_status get(double** p, size_t count) {
+    hipError_t e = hipHostMalloc((void**)p, std::max<size_t>(count, 32) * sizeof(double));
+    if (e != hipSuccess) return fail(FE_ENOMEM, "fe_krylov_schur: hipHostMalloc failed");
+    ptrs.push_back(*p);
+    return FE_OK;
+  }
+};
+
+// upper-triangular inverse of the na x na matrix R (row-major, ld = ld)
+static void inv_upper(int na, const double* R, int ld, double* Ri, int ldi) {
+  for (int i = 0; i < na; ++i)
+    for (int j = 0; j < na; ++j) Ri[i * ldi + j] = 0.0;
+  for (int j = 0; j < na; ++j) {
+    Ri[j * ldi + j] = 1.0 / R[j * ld + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int t = i + 1; t <= j; ++t) s += R[i * ld + t] * Ri[t * ldi + j];
+      Ri[i * ldi + j] = -s / R[i * ld + i];
+    }
+  }
+}
+
+class Solver {
+ public:
+  const Csr& A;
+  int nev, b, m;
+  double tol, eta;
+  fe_ks_opts o;
+  hipStream_t s;
+  fe_dtype dt;
+  size_t es;
+  int64_t n, stride;
+  char* V = nullptr;  // m/b + 1 blocks
+  double *dC = nullptr, *dM = nullptr, *dY = nullptr, *dTheta = nullptr, *dSums = nullptr;
+  double *dPart = nullptr, *dPartRes = nullptr;
+  double *hC1 = nullptr, *hC2 = nullptr, *hG = nullptr, *hM = nullptr, *hY = nullptr,
+         *hSums = nullptr, *hTheta = nullptr;
+  DevBuf dev;
+  HostBuf host;
+  Prof prof;
+  std::vector<double> T, Bk;
+  int step = 0, refills = 0, spmm_calls = 0, spmm_cols = 0, gram_calls = 0, update_calls = 0;
+  double t_host = 0.0;
+  double bytes[4] = {0, 0, 0, 0};  // algorithmic HBM bytes per kernel class
+
+  Solver(const Csr& A_, int nev_, int b_, int m_, double tol_, const fe_ks_opts& o_)
+      : A(A_), nev(nev_), b(b_), m(m_), tol(tol_), o(o_) {
+    s = (hipStream_t)o.hip_stream;
+    dt = o.dt;
+    es = dtype_size(dt);
+    n = A.n;
+    stride = n * b;
+    eta = o.eta > 0 ? o.eta : (dt == FE_F64 ? 1e-6 : dt == FE_F32 ? 1e-5 : 3e-2);
+    prof.on = o.profile != 0;
+    prof.s = s;
+  }
+
+  void* blk(int j) { return V + (size_t)j * stride * es; }
+
+  fe_status setup() {
+    const int nblk = m / b + 1;
+    FE_TRY(dev.get((void**)&V, (size_t)nblk * stride * es));
+    const int kmax = m + b;
+    FE_TRY(dev.get((void**)&dC, sizeof(double) * 2 * kmax * b));
+    FE_TRY(dev.get((void**)&dM, sizeof(double) * b * b));
+    FE_TRY(dev.get((void**)&dY, sizeof(double) * m * m));
+    FE_TRY(dev.get((void**)&dTheta, sizeof(double) * 64));
+    FE_TRY(dev.get((void**)&dSums, sizeof(double) * 3 * 64));
+    FE_TRY(dev.get((void**)&dPart, sizeof(double) * gram_partials_doubles(n, kmax, b)));
+    FE_TRY(dev.get((void**)&dPartRes, sizeof(double) * resid_partials_doubles(n, 64)));
+    FE_TRY(host.get(&hC1, kmax * b));
+    FE_TRY(host.get(&hC2, kmax * b));
+    FE_TRY(host.get(&hG, kmax * b));
+    FE_TRY(host.get(&hM, b * b));
+    FE_TRY(host.get(&hY, m * m));
+    FE_TRY(host.get(&hSums, 3 * 64));
+    FE_TRY(host.get(&hTheta, 64));
+    T.assign((size_t)m * m, 0.0);
+    Bk.assign((size_t)b * m, 0.0);
+    return FE_OK;
+  }
+
+  fe_status sync() {
+    FE_HIP(hipStreamSynchronize(s));
+    prof.flush();
+    return FE_OK;
+  }
+
+  fe_status gram(int nblk, const void* W, double* C) {
+    prof.begin(P_GRAM);
+    fe_status st = gram_launch(V, nblk, stride, W, n, b, dt, 1.0, C, dPart, s);
+    prof.end();
+    ++gram_calls;
+    bytes[P_GRAM] += (double)n * nblk * b * es;  // W is the last of the nblk blocks
+    return st;
+  }
+  fe_status update(void* W, const void* Vp, int nblk, const double* C, double alpha, double beta) {
+    prof.begin(P_UPDATE);
+    fe_status st = update_launch(W, n, b, Vp, nblk, stride, C, alpha, beta, dt, s);
+    prof.end();
+    ++update_calls;
+    const bool in_place = (W == Vp);
+    bytes[P_UPDATE] += (double)n * b * es * ((in_place ? 0 : nblk) + (beta != 0.0 || in_place) + 1);
+    return st;
+  }
+  fe_status spmm(const void* X, void* Y, int cols) {
+    prof.begin(P_SPMM);
+    fe_status st = spmm_launch(A, X, Y, cols, dt, s);
+    prof.end();
+    spmm_cols += cols;
+    bytes[P_SPMM] += 4.0 * A.nnz + 8.0 * (n + 1) + 2.0 * n * cols * es;
+    return st;
+  }
+  fe_status upload_M() {
+    FE_HIP(hipMemcpyAsync(dM, hM, sizeof(double) * b * b, hipMemcpyHostToDevice, s));
+    return FE_OK;
+  }
+  // W <- W * hM (in place)
+  fe_status right_mult(void* W) {
+    FE_TRY(upload_M());
+    return update(W, W, 1, dM, 1.0, 0.0);
+  }
+  // G = W^T W of block wb into hG (synchronises)
+  fe_status self_gram(int wb) {
+    prof.begin(P_GRAM);
+    FE_TRY(gram_launch(blk(wb), 1, stride, blk(wb), n, b, dt, 1.0, dC, dPart, s));
+    prof.end();
+    ++gram_calls;
+    bytes[P_GRAM] += (double)n * b * es;
+    FE_HIP(hipMemcpyAsync(hG, dC, sizeof(double) * b * b, hipMemcpyDeviceToHost, s));
+    return sync();
+  }
+
+  // Orthogonalise W (block wb) against V[:, :k] (blocks 0..k/b-1, k = wb*b) and
+  // orthonormalise it.  Out: C (k x b) and R (b x b) with W_in = V C + Q R.
+  fe_status orth_block(int wb, std::vector<double>& C, std::vector<double>& R) {
+    const int nk = wb;  // basis blocks
+    const int k = nk * b;
+    void* W = blk(wb);
+    double* dC1 = dC;
+    double* dC2 = dC + (size_t)(k + b) * b;
+    // pass 1: [V W]^T W
+    FE_TRY(gram(nk + 1, W, dC1));
+    FE_HIP(hipMemcpyAsync(hC1, dC1, sizeof(double) * (k + b) * b, hipMemcpyDeviceToHost, s));
+    if (nk > 0) {
+      FE_TRY(update(W, V, nk, dC1, -1.0, 1.0));
+      FE_TRY(gram(nk + 1, W, dC2));
+      FE_HIP(hipMemcpyAsync(hC2, dC2, sizeof(double) * (k + b) * b, hipMemcpyDeviceToHost, s));
+      FE_TRY(update(W, V, nk, dC2, -1.0, 1.0));
+    }
+    FE_TRY(sync());
+    auto th = clk::now();
+    std::vector<double> nb(b), G((size_t)b * b);
+    for (int j = 0; j < b; ++j) nb[j] = std::sqrt(std::max(0.0, hC1[(size_t)(k + j) * b + j]));
+    C.assign((size_t)k * b, 0.0);
+    if (nk > 0) {
+      for (int i = 0; i < k * b; ++i) C[i] = hC1[i] + hC2[i];
+      // G = W2^T W2 = W1^T W1 - C2^T C2 (V orthonormal)
+      for (int i = 0; i < b; ++i)
+        for (int j = 0; j < b; ++j) {
+          double g = hC2[(size_t)(k + i) * b + j];
+          for (int t = 0; t < k; ++t) g -= hC2[(size_t)t * b + i] * hC2[(size_t)t * b + j];
+          G[i * b + j] = g;
+        }
+    } else {
+      for (int i = 0; i < b * b; ++i) G[i] = hC1[i];
+    }
+    // rank-revealing Cholesky in column order
+    std::vector<double> R1((size_t)b * b, 0.0);
+    std::vector<int> acc, dep;
+    for (int j = 0; j < b; ++j) {
+      double d = G[j * b + j];
+      for (int i : acc) d -= R1[i * b + j] * R1[i * b + j];
+      const double thr = eta * nb[j];
+      if (!(d > thr * thr) || !(d > 0.0)) {
+        dep.push_back(j);
+        continue;
+      }
+      const double rjj = std::sqrt(d);
+      R1[j * b + j] = rjj;
+      for (int l = j + 1; l < b; ++l) {
+        double g = G[j * b + l];
+        for (int i : acc) g -= R1[i * b + j] * R1[i * b + l];
+        R1[j * b + l] = g / rjj;
+      }
+      acc.push_back(j);
+    }
+    const int na = (int)acc.size();
+    // M = R1[acc,acc]^-1 scattered into acc positions (dependent columns -> 0)
+    {
+      std::vector<double> Ra((size_t)na * na), Rai((size_t)na * na);
+      for (int s1 = 0; s1 < na; ++s1)
+        for (int s2 = 0; s2 < na; ++s2) Ra[s1 * na + s2] = R1[acc[s1] * b + acc[s2]];
+      inv_upper(na, Ra.data(), na, Rai.data(), na);
+      std::fill(hM, hM + b * b, 0.0);
+      for (int s1 = 0; s1 < na; ++s1)
+        for (int s2 = 0; s2 < na; ++s2) hM[acc[s1] * b + acc[s2]] = Rai[s1 * na + s2];
+    }
+    t_host += secs(th, clk::now());
+    FE_TRY(right_mult(W));
+    // Racc (na x na): accumulated second-stage factor of the accepted columns
+    std::vector<double> Racc((size_t)na * na, 0.0);
+    for (int i = 0; i < na; ++i) Racc[i * na + i] = 1.0;
+    std::vector<int> ord = acc;
+    if (!dep.empty()) {
+      uint32_t mask = 0;
+      for (int j : dep) mask |= 1u << j;
+      FE_TRY(random_fill(W, n, b, mask, 1, o.seed, (uint32_t)step, A.relabeled ? A.d_perm : nullptr,
+                         dt, s));
+      if (nk > 0) {  // project the refills (and, harmlessly, the rest) against V, twice
+        for (int pass = 0; pass < 2; ++pass) {
+          FE_TRY(gram(nk + 1, W, dC2));
+          FE_TRY(update(W, V, nk, dC2, -1.0, 1.0));
+        }
+      }
+      refills += (int)dep.size();
+      for (int j : dep) ord.push_back(j);
+    }
+    // Cholesky QR passes in the order `ord` (accepted first): two passes, or
+    // three when refills were added (the refills start far from orthogonal)
+    const int passes = dep.empty() ? 1 : 2;
+    for (int pass = 0; pass < passes; ++pass) {
+      FE_TRY(self_gram(wb));
+      auto th2 = clk::now();
+      std::vector<double> Gp((size_t)b * b), Rp((size_t)b * b, 0.0), Rpi((size_t)b * b);
+      for (int s1 = 0; s1 < b; ++s1)
+        for (int s2 = 0; s2 < b; ++s2) Gp[s1 * b + s2] = hG[ord[s1] * b + ord[s2]];
+      for (int j = 0; j < b; ++j) {
+        double d = Gp[j * b + j];
+        for (int i = 0; i < j; ++i) d -= Rp[i * b + j] * Rp[i * b + j];
+        if (!(d > 0.0))
+          return fail(FE_EBREAKDOWN, "fe_krylov_schur: block QR lost rank (step %d)", step);
+        Rp[j * b + j] = std::sqrt(d);
+        for (int l = j + 1; l < b; ++l) {
+          double g = Gp[j * b + l];
+          for (int i = 0; i < j; ++i) g -= Rp[i * b + j] * Rp[i * b + l];
+          Rp[j * b + l] = g / Rp[j * b + j];
+        }
+      }
+      inv_upper(b, Rp.data(), b, Rpi.data(), b);
+      for (int s1 = 0; s1 < b; ++s1)
+        for (int s2 = 0; s2 < b; ++s2) hM[ord[s1] * b + ord[s2]] = Rpi[s1 * b + s2];
+      // Racc <- Rp[:na,:na] * Racc
+      std::vector<double> tmp((size_t)na * na, 0.0);
+      for (int i = 0; i < na; ++i)
+        for (int j = 0; j < na; ++j) {
+          double sum = 0.0;
+          for (int t = 0; t < na; ++t) sum += Rp[i * b + t] * Racc[t * na + j];
+          tmp[i * na + j] = sum;
+        }
+      Racc.swap(tmp);
+      t_host += secs(th2, clk::now());
+      FE_TRY(right_mult(W));
+    }
+    // R[acc[i], :] = sum_t Racc[i][t] R1[acc[t], :], dependent rows 0
+    R.assign((size_t)b * b, 0.0);
+    for (int i = 0; i < na; ++i)
+      for (int j = 0; j < b; ++j) {
+        double sum = 0.0;
+        for (int t = 0; t < na; ++t) sum += Racc[i * na + t] * R1[acc[t] * b + j];
+        R[acc[i] * b + j] = sum;
+      }
+    return FE_OK;
+  }
+
+  fe_status run(double* evals, void* evecs, fe_ks_report* rep) {
+    auto t0 = clk::now();
+    FE_TRY(setup());
+    const int max_restarts = o.max_restarts > 0 ? o.max_restarts : 500;
+    const int32_t* perm = A.relabeled ? A.d_perm : nullptr;
+    // start block into block 0 (internal numbering)
+    prof.begin(P_OTHER);
+    if (o.start) {
+      if (perm)
+        FE_TRY(permute_rows(blk(0), o.start, perm, n, b, dt, false, s));
+      else
+        FE_TRY(copy_block(blk(0), o.start, n, b, dt, s));
+    } else {
+      FE_TRY(random_fill(blk(0), n, b, 0xFFFFFFFFu, 0, o.seed, 0, perm, dt, s));
+    }
+    prof.end();
+    std::vector<double> C, R;
+    step = 0;
+    FE_TRY(orth_block(0, C, R));
+    int k = 0;  // basis columns; Q is block k/b
+    int restarts = 0;
+    std::vector<double> theta(m), Y((size_t)m * m), rho(m);
+    bool converged = false;
+    int nconv = 0;
+    for (;;) {
+      while (k < m) {
+        k += b;
+        const int wb = k / b;
+        FE_TRY(spmm(blk(wb - 1), blk(wb), b));
+        ++spmm_calls;
+        ++step;
+        FE_TRY(orth_block(wb, C, R));
+        auto th = clk::now();
+        for (int i = 0; i < k; ++i)
+          for (int j = 0; j < b; ++j) {
+            T[(size_t)i * m + (k - b + j)] = C[(size_t)i * b + j];
+            T[(size_t)(k - b + j) * m + i] = C[(size_t)i * b + j];
+          }
+        std::fill(Bk.begin(), Bk.end(), 0.0);
+        for (int i = 0; i < b; ++i)
+          for (int j = 0; j < b; ++j) Bk[(size_t)i * m + (k - b + j)] = R[(size_t)i * b + j];
+        t_host += secs(th, clk::now());
+      }
+      // Rayleigh-Ritz on the symmetric part of T
+      auto th = clk::now();
+      std::vector<double> S((size_t)m * m), w(m), Z((size_t)m * m);
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) S[(size_t)i * m + j] = 0.5 * (T[(size_t)i * m + j] + T[(size_t)j * m + i]);
+      if (!sym_eig(m, S.data(), w.data(), Z.data()))
+        return fail(FE_ENOCONV, "fe_krylov_schur: projected eigenproblem did not converge");
+      std::vector<int> idx(m);
+      for (int i = 0; i < m; ++i) idx[i] = i;
+      std::sort(idx.begin(), idx.end(), [&](int a, int c) {
+        const double fa = std::fabs(w[a]), fc = std::fabs(w[c]);
+        if (fa != fc) return fa > fc;
+        if (w[a] != w[c]) return w[a] > w[c];
+        return a < c;
+      });
+      for (int j = 0; j < m; ++j) {
+        theta[j] = w[idx[j]];
+        for (int i = 0; i < m; ++i) Y[(size_t)i * m + j] = Z[(size_t)i * m + idx[j]];
+      }
+      nconv = 0;
+      for (int j = 0; j < m; ++j) {
+        double r2 = 0.0;
+        for (int i = 0; i < b; ++i) {
+          double sum = 0.0;
+          for (int t = 0; t < m; ++t) sum += Bk[(size_t)i * m + t] * Y[(size_t)t * m + j];
+          r2 += sum * sum;
+        }
+        rho[j] = std::sqrt(r2) / ritz_scale(theta[j]);
+        if (j < nev && rho[j] <= tol) ++nconv;
+      }
+      converged = nconv == nev;
+      t_host += secs(th, clk::now());
+      if (o.verbose) {
+        double worst = 0.0;
+        for (int j = 0; j < nev; ++j) worst = std::max(worst, rho[j]);
+        fprintf(stderr, "[fe_krylov_schur] restart %d spmm %d conv %d/%d max rho %.3e theta0 %.12g\n",
+                restarts, spmm_calls, nconv, nev, worst, theta[0]);
+      }
+      if (converged || restarts >= max_restarts) break;
+      // restart
+      const int p = m - b * std::max(1, (m - nev) / (2 * b));
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < p; ++j) hY[(size_t)i * p + j] = Y[(size_t)i * m + j];
+      FE_HIP(hipMemcpyAsync(dY, hY, sizeof(double) * m * p, hipMemcpyHostToDevice, s));
+      prof.begin(P_OTHER);
+      FE_TRY(rotate_launch(V, n, b, m / b, p / b, stride, dY, dt, s));
+      FE_TRY(copy_block(blk(p / b), blk(m / b), n, b, dt, s));
+      prof.end();
+      std::vector<double> Bn((size_t)b * m, 0.0);
+      for (int i = 0; i < b; ++i)
+        for (int j = 0; j < p; ++j) {
+          double sum = 0.0;
+          for (int t = 0; t < m; ++t) sum += Bk[(size_t)i * m + t] * Y[(size_t)t * m + j];
+          Bn[(size_t)i * m + j] = sum;
+        }
+      Bk.swap(Bn);
+      std::fill(T.begin(), T.end(), 0.0);
+      for (int j = 0; j < p; ++j) T[(size_t)j * m + j] = theta[j];
+      k = p;
+      ++restarts;
+      FE_TRY(sync());  // hY reused next restart
+    }
+    // final check in FP64: X = V Y[:, :nev], AX = A X, Rayleigh quotients and
+    // explicit residuals (the solver's own check of its answer)
+    double *X = nullptr, *AX = nullptr;
+    FE_TRY(dev.get((void**)&X, (size_t)n * nev * sizeof(double)));
+    FE_TRY(dev.get((void**)&AX, (size_t)n * nev * sizeof(double)));
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < nev; ++j) hY[(size_t)i * nev + j] = Y[(size_t)i * m + j];
+    for (int j = 0; j < nev; ++j) hTheta[j] = 0.0;
+    FE_HIP(hipMemcpyAsync(dY, hY, sizeof(double) * m * nev, hipMemcpyHostToDevice, s));
+    FE_HIP(hipMemcpyAsync(dTheta, hTheta, sizeof(double) * nev, hipMemcpyHostToDevice, s));
+    prof.begin(P_OTHER);
+    FE_TRY(combine_launch(X, nev, n, b, V, m / b, stride, dY, dt, s));
+    prof.end();
+    prof.begin(P_OTHER);
+    FE_TRY(spmm_launch(A, X, AX, nev, FE_F64, s));
+    prof.end();
+    spmm_cols += nev;
+    prof.begin(P_OTHER);
+    FE_TRY(resid_launch(AX, X, n, nev, dTheta, dSums, dPartRes, s));
+    prof.end();
+    FE_HIP(hipMemcpyAsync(hSums, dSums, sizeof(double) * 3 * nev, hipMemcpyDeviceToHost, s));
+    FE_TRY(sync());
+    std::vector<double> rq(nev), xx(nev);
+    for (int j = 0; j < nev; ++j) {
+      xx[j] = hSums[3 * j + 1];
+      rq[j] = hSums[3 * j] / xx[j];
+      hTheta[j] = rq[j];
+    }
+    FE_HIP(hipMemcpyAsync(dTheta, hTheta, sizeof(double) * nev, hipMemcpyHostToDevice, s));
+    prof.begin(P_OTHER);
+    FE_TRY(resid_launch(AX, X, n, nev, dTheta, dSums, dPartRes, s));
+    if (evecs) FE_TRY(store_rows(evecs, X, perm, n, nev, dt, s));
+    prof.end();
+    FE_HIP(hipMemcpyAsync(hSums, dSums, sizeof(double) * 3 * nev, hipMemcpyDeviceToHost, s));
+    FE_TRY(sync());
+    for (int j = 0; j < nev; ++j) evals[j] = rq[j];
+    if (rep) {
+      std::memset(rep, 0, sizeof(*rep));
+      rep->restarts = restarts;
+      rep->spmm_calls = spmm_calls;
+      rep->spmm_cols = spmm_cols;
+      rep->converged = nconv;
+      rep->refills = refills;
+      rep->gram_calls = gram_calls;
+      rep->update_calls = update_calls;
+      for (int j = 0; j < nev; ++j) {
+        rep->rho[j] = rho[j];
+        rep->ritz[j] = theta[j];
+        rep->resid[j] = std::sqrt(std::max(0.0, hSums[3 * j + 2])) /
+                        (ritz_scale(rq[j]) * std::sqrt(xx[j]));
+      }
+      rep->t_spmm = prof.t[P_SPMM];
+      rep->t_gram = prof.t[P_GRAM];
+      rep->t_update = prof.t[P_UPDATE];
+      rep->t_other_dev = prof.t[P_OTHER];
+      rep->bytes_spmm = bytes[P_SPMM];
+      rep->bytes_gram = bytes[P_GRAM];
+      rep->bytes_update = bytes[P_UPDATE];
+      rep->t_host = t_host;
+      rep->t_total = secs(t0, clk::now());
+    }
+    return converged ? FE_OK : fail(FE_ENOCONV, "fe_krylov_schur: %d of %d pairs converged after %d restarts", nconv, nev, restarts);
+  }
+};
+
+}  // namespace
+}  // namespace fe
+
+extern "C" fe_status fe_krylov_schur(const fe_csr* A, int32_t nev, int32_t block, int32_t m,
+                                     double tol, const fe_ks_opts* opts, double* evals,
+                                     void* evecs, fe_ks_report* rep) {
+  using namespace fe;
+  if (!A || !evals) return fail(FE_EINVAL, "fe_krylov_schur: NULL argument");
+  fe_ks_opts o;
+  std::memset(&o, 0, sizeof o);
+  if (opts) o = *opts;
+  if (!dtype_ok(o.dt)) return fail(FE_EINVAL, "fe_krylov_schur: bad dtype");
+  if (block < 1 || block > 16 || m < 1 || m % block || nev < 1 || nev > m - block || !(tol > 0))
+    return fail(FE_EINVAL, "fe_krylov_schur: need 1<=block<=16, m %% block == 0, 1<=nev<=m-block, tol>0");
+  if (o.which != 0) return fail(FE_EUNSUPPORTED, "fe_krylov_schur: only largest magnitude");
+  const int p = m - block * std::max(1, (m - nev) / (2 * block));
+  if (m > 128 || p > 64 || nev > 64 || (size_t)m * p * 8 > 64 * 1024)
+    return fail(FE_EUNSUPPORTED, "fe_krylov_schur: m=%d keeps p=%d (limits m<=128, p<=64)", m, p);
+  if (block != 1 && block != 2 && block != 4 && block != 8 && block != 16)
+    return fail(FE_EUNSUPPORTED, "fe_krylov_schur: block must be 1, 2, 4, 8 or 16");
+  if ((int64_t)m + block > A->n) return fail(FE_EINVAL, "fe_krylov_schur: m + block > n");
+  clear_error();
+  Solver S(*A, nev, block, m, tol, o);
+  return S.run(evals, evecs, rep);
+}

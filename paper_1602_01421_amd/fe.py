@@ -1,0 +1,305 @@
+"""Thin ctypes binding of libfe.so (names follow the C ABI in include/fe.h).
+
+Only argument marshalling happens here: every step of the sparse product,
+the Gram/update kernels and the Krylov-Schur iteration runs in the HIP
+library.  PyTorch supplies device memory (tensors) and streams.  If the
+library is not built, every entry point raises FeError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfe.so")
+
+FE_OK, FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_ENOCONV, FE_EBREAKDOWN, FE_EUNSUPPORTED = range(7)
+FE_F64, FE_F32, FE_BF16 = 0, 1, 2
+FE_SYMMETRIZE, FE_DEDUPE, FE_DROP_SELF, FE_RELABEL_BY_DEGREE = 0x1, 0x2, 0x4, 0x8
+FE_GRAPH_DEFAULT = FE_SYMMETRIZE | FE_DEDUPE | FE_DROP_SELF
+
+EXPORTED = ("fe_last_error", "fe_version", "fe_csr_build", "fe_csr_from_csr", "fe_csr_info",
+            "fe_csr_perm", "fe_csr_export", "fe_csr_free", "fe_spmm", "fe_gram",
+            "fe_block_update", "fe_krylov_schur", "fe_dense_symeig")
+
+
+class FeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fe status {status}: {msg}")
+        self.status = status
+
+
+class KsOpts(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_int32), ("which", ctypes.c_int32),
+                ("max_restarts", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("start", ctypes.c_void_p), ("hip_stream", ctypes.c_void_p),
+                ("eta", ctypes.c_double), ("profile", ctypes.c_int32),
+                ("verbose", ctypes.c_int32)]
+
+
+class KsReport(ctypes.Structure):
+    _fields_ = [("restarts", ctypes.c_int32), ("spmm_calls", ctypes.c_int32),
+                ("spmm_cols", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("refills", ctypes.c_int32), ("gram_calls", ctypes.c_int32),
+                ("update_calls", ctypes.c_int32),
+                ("rho", ctypes.c_double * 64), ("ritz", ctypes.c_double * 64),
+                ("resid", ctypes.c_double * 64),
+                ("t_spmm", ctypes.c_double), ("t_gram", ctypes.c_double),
+                ("t_update", ctypes.c_double), ("t_other_dev", ctypes.c_double),
+                ("bytes_spmm", ctypes.c_double), ("bytes_gram", ctypes.c_double),
+                ("bytes_update", ctypes.c_double),
+                ("t_host", ctypes.c_double), ("t_total", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfe.so (raises FeError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FeError(FE_EDEVICE, f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u32, f64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                 ctypes.c_uint32, ctypes.c_double)
+        L.fe_last_error.restype = ctypes.c_char_p
+        L.fe_version.restype = i32
+        sig = {
+            "fe_csr_build": [i64, i64, P, P, u32, ctypes.POINTER(P)],
+            "fe_csr_from_csr": [i64, P, P, u32, ctypes.POINTER(P)],
+            "fe_csr_info": [P, P, P, P],
+            "fe_csr_perm": [P, P],
+            "fe_csr_export": [P, P, P],
+            "fe_spmm": [P, P, P, i32, i32, P],
+            "fe_gram": [P, i32, i64, P, i64, i32, i32, f64, P, P],
+            "fe_block_update": [P, i64, i32, P, i32, i64, P, f64, f64, i32, P],
+            "fe_krylov_schur": [P, i32, i32, i32, f64, ctypes.POINTER(KsOpts), P, P,
+                                ctypes.POINTER(KsReport)],
+            "fe_dense_symeig": [i32, P, P, P],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = i32
+        L.fe_csr_free.argtypes = [P]
+        L.fe_csr_free.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(st: int, allow=()):
+    if st != FE_OK and st not in allow:
+        raise FeError(st, lib().fe_last_error().decode())
+    return st
+
+
+def _np_ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _dt_of(t) -> int:
+    import torch
+    m = {torch.float64: FE_F64, torch.float32: FE_F32, torch.bfloat16: FE_BF16}
+    if t.dtype not in m:
+        raise FeError(FE_EINVAL, f"unsupported dtype {t.dtype}")
+    return m[t.dtype]
+
+
+def torch_dtype(dt: int):
+    import torch
+    return {FE_F64: torch.float64, FE_F32: torch.float32, FE_BF16: torch.bfloat16}[dt]
+
+
+def _dev_ptr(t):
+    if not t.is_cuda:
+        raise FeError(FE_EINVAL, "tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise FeError(FE_EINVAL, "tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+def version() -> int:
+    return int(lib().fe_version())
+
+
+class Csr:
+    """Owning wrapper of an fe_csr handle."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+        n, nnz, md = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().fe_csr_info(self._h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(md)))
+        self.n, self.nnz, self.max_deg = n.value, nnz.value, md.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def perm(self) -> np.ndarray:
+        p = np.empty(self.n, dtype=np.int32)
+        _check(lib().fe_csr_perm(self._h, _np_ptr(p)))
+        return p
+
+    def export(self):
+        rp = np.empty(self.n + 1, dtype=np.int64)
+        ci = np.empty(max(self.nnz, 1), dtype=np.int32)
+        _check(lib().fe_csr_export(self._h, _np_ptr(rp), _np_ptr(ci)))
+        return rp, ci[: self.nnz]
+
+    def close(self):
+        if self._h:
+            lib().fe_csr_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fe_csr_build(n: int, src: np.ndarray, dst: np.ndarray, flags: int = FE_GRAPH_DEFAULT) -> Csr:
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    if src.shape != dst.shape:
+        raise FeError(FE_EINVAL, "src/dst length mismatch")
+    h = ctypes.c_void_p()
+    _check(lib().fe_csr_build(n, src.shape[0], _np_ptr(src), _np_ptr(dst), flags, ctypes.byref(h)))
+    return Csr(h)
+
+
+def fe_csr_from_csr(n: int, row_ptr: np.ndarray, col_idx: np.ndarray, flags: int = 0) -> Csr:
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    if ci.size == 0:
+        ci = np.zeros(1, dtype=np.int32)
+    h = ctypes.c_void_p()
+    _check(lib().fe_csr_from_csr(n, _np_ptr(rp), _np_ptr(ci), flags, ctypes.byref(h)))
+    return Csr(h)
+
+
+def fe_spmm(A: Csr, X, Y=None, stream=None):
+    """Y = A X for a device tensor X of shape (n, b); returns Y."""
+    import torch
+    if X.dim() != 2 or X.shape[0] != A.n:
+        raise FeError(FE_EINVAL, f"X must be ({A.n}, b)")
+    if Y is None:
+        Y = torch.empty_like(X)
+    _check(lib().fe_spmm(A.handle, _dev_ptr(X), _dev_ptr(Y), X.shape[1], _dt_of(X), _stream(stream)))
+    return Y
+
+
+def fe_gram(V, W, alpha: float = 1.0, C=None, stream=None):
+    """C = alpha V^T W.  V: (nblk, n, b) device tensor (packed blocks), W: (n, b)."""
+    import torch
+    nblk, n, b = V.shape
+    if W.shape != (n, b) or W.dtype != V.dtype:
+        raise FeError(FE_EINVAL, "W must be (n, b) with V's dtype")
+    if C is None:
+        C = torch.empty((nblk * b, b), dtype=torch.float64, device=V.device)
+    _check(lib().fe_gram(_dev_ptr(V), nblk, n * b, _dev_ptr(W), n, b, _dt_of(V), alpha,
+                         _dev_ptr(C), _stream(stream)))
+    return C
+
+
+def fe_block_update(W, V, C, alpha: float = 1.0, beta: float = 1.0, stream=None):
+    """W <- beta W + alpha V C.  V: (nblk, n, b) (or W itself for in-place), C: (k, b) FP64."""
+    n, b = W.shape
+    if V.dim() == 2:
+        nblk = 1
+    else:
+        nblk = V.shape[0]
+        if V.shape[1:] != (n, b):
+            raise FeError(FE_EINVAL, "V blocks must be (n, b)")
+    if C.shape != (nblk * b, b) or C.dtype != __import__("torch").float64:
+        raise FeError(FE_EINVAL, "C must be (k, b) float64")
+    _check(lib().fe_block_update(_dev_ptr(W), n, b, _dev_ptr(V), nblk, n * b, _dev_ptr(C), alpha,
+                                 beta, _dt_of(W), _stream(stream)))
+    return W
+
+
+@dataclass
+class KsResult:
+    evals: np.ndarray
+    evecs: object
+    status: int
+    restarts: int
+    spmm_calls: int
+    spmm_cols: int
+    converged: int
+    refills: int
+    gram_calls: int
+    update_calls: int
+    rho: np.ndarray
+    ritz: np.ndarray
+    resid: np.ndarray
+    t_spmm: float
+    t_gram: float
+    t_update: float
+    t_other_dev: float
+    bytes_spmm: float
+    bytes_gram: float
+    bytes_update: float
+    t_host: float
+    t_total: float
+
+
+def fe_krylov_schur(A: Csr, nev: int, block: int, m: int, tol: float, dtype=None, start=None,
+                    seed: int = 0, max_restarts: int = 0, eta: float = 0.0, stream=None,
+                    want_vectors: bool = True, profile: bool = False,
+                    verbose: bool = False) -> KsResult:
+    """Block Krylov-Schur for the nev largest-magnitude eigenpairs (see fe.h)."""
+    import torch
+    if dtype is None:
+        dtype = torch.float64
+    dt = {torch.float64: FE_F64, torch.float32: FE_F32, torch.bfloat16: FE_BF16}[dtype]
+    o = KsOpts()
+    o.dt = dt
+    o.which = 0
+    o.max_restarts = max_restarts
+    o.seed = seed
+    o.eta = eta
+    o.profile = int(profile)
+    o.verbose = int(verbose)
+    o.hip_stream = _stream(stream).value
+    if start is not None:
+        if start.shape != (A.n, block) or start.dtype != dtype:
+            raise FeError(FE_EINVAL, "start must be (n, block) in the solve dtype")
+        o.start = _dev_ptr(start).value
+    evals = np.zeros(nev, dtype=np.float64)
+    evecs = torch.empty((A.n, nev), dtype=dtype, device="cuda") if want_vectors else None
+    rep = KsReport()
+    st = lib().fe_krylov_schur(A.handle, nev, block, m, tol, ctypes.byref(o), _np_ptr(evals),
+                               _dev_ptr(evecs) if evecs is not None else None, ctypes.byref(rep))
+    _check(st, allow=(FE_ENOCONV,))
+    return KsResult(evals=evals, evecs=evecs, status=st, restarts=rep.restarts,
+                    spmm_calls=rep.spmm_calls, spmm_cols=rep.spmm_cols,
+                    converged=rep.converged, refills=rep.refills, gram_calls=rep.gram_calls,
+                    update_calls=rep.update_calls, rho=np.array(rep.rho[:nev]),
+                    ritz=np.array(rep.ritz[:nev]),
+                    resid=np.array(rep.resid[:nev]), t_spmm=rep.t_spmm, t_gram=rep.t_gram,
+                    t_update=rep.t_update, t_other_dev=rep.t_other_dev,
+                    bytes_spmm=rep.bytes_spmm, bytes_gram=rep.bytes_gram,
+                    bytes_update=rep.bytes_update, t_host=rep.t_host,
+                    t_total=rep.t_total)
+
+
+def fe_dense_symeig(a: np.ndarray):
+    """Host eigendecomposition of a small symmetric matrix: (w, z), unordered."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    n = a.shape[0]
+    w = np.empty(n)
+    z = np.empty((n, n))
+    _check(lib().fe_dense_symeig(n, _np_ptr(a), _np_ptr(w), _np_ptr(z)))
+    return w, z

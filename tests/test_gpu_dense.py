@@ -1,0 +1,116 @@
+"""Parity of fe_gram (C = alpha V^T W) and fe_block_update (W = beta W + alpha V C).
+
+Bars: small-integer inputs bitwise (exact in FP64 arithmetic and in the
+storage dtype); N(0,1) inputs: Gram within 1e-13 * sum |V||W| of the FP64
+oracle on the same stored values; update within one storage ulp plus
+1e-13 * sum of |terms|.
+"""
+import numpy as np
+import pytest
+import torch
+
+import fe_synth as S
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+DT = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+ULP = {"f64": 2.0 ** -52, "f32": 2.0 ** -23, "bf16": 2.0 ** -7}
+
+
+def dev(x, dt):
+    return torch.tensor(np.asarray(x), dtype=torch.float64).to(dt).cuda()
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n,nblk,b", [(1, 1, 1), (37, 3, 4), (1000, 13, 4), (4097, 6, 8),
+                                      (777, 2, 16), (5000, 5, 3), (300, 1, 64), (70001, 12, 4)])
+def test_gram_small_int_bitwise(fe, dt, n, nblk, b):
+    V = S.small_ints((nblk, n, b), seed=1, lo=-4, hi=4)
+    W = S.small_ints((n, b), seed=2, lo=-4, hi=4)
+    C = host(fe.fe_gram(dev(V, DT[dt]), dev(W, DT[dt]), alpha=2.0))
+    Vf = V.transpose(1, 0, 2).reshape(n, nblk * b)  # column p = block p // b, col p % b
+    assert np.array_equal(C, O.gram(Vf, W, alpha=2.0))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n,nblk,b", [(4099, 13, 4), (100003, 7, 8), (5000, 3, 16), (2000, 20, 2)])
+def test_gram_normal(fe, dt, n, nblk, b):
+    Vd = dev(S.normal((nblk, n, b), seed=3), DT[dt])
+    Wd = dev(S.normal((n, b), seed=4), DT[dt])
+    V, W = host(Vd), host(Wd)
+    Vf = V.transpose(1, 0, 2).reshape(n, nblk * b)
+    want = O.gram(Vf, W)
+    bound = 1e-13 * (np.abs(Vf).T @ np.abs(W))
+    C = host(fe.fe_gram(Vd, Wd))
+    assert np.all(np.abs(C - want) <= bound)
+    C2 = host(fe.fe_gram(Vd, Wd))
+    assert np.array_equal(C, C2)  # fixed reduction order
+
+
+def test_gram_w_is_a_block_of_v(fe):
+    V = dev(S.normal((5, 3000, 4), seed=5), torch.float32)
+    C = host(fe.fe_gram(V, V[4]))
+    Vf = host(V).transpose(1, 0, 2).reshape(3000, 20)
+    assert np.allclose(C, Vf.T @ Vf[:, 16:20], rtol=1e-12, atol=1e-10)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n,nblk,b", [(1, 1, 1), (1000, 3, 4), (4097, 12, 8), (999, 2, 16),
+                                      (500, 3, 5), (300, 2, 64)])
+def test_update_small_int_bitwise(fe, dt, n, nblk, b):
+    V = S.small_ints((nblk, n, b), seed=6, lo=-3, hi=3)
+    W = S.small_ints((n, b), seed=7, lo=-3, hi=3)
+    C = S.small_ints((nblk * b, b), seed=8, lo=-3, hi=3)
+    Wd = dev(W, DT[dt])
+    fe.fe_block_update(Wd, dev(V, DT[dt]), dev(C, torch.float64), alpha=-1.0, beta=2.0)
+    Vf = V.transpose(1, 0, 2).reshape(n, nblk * b)
+    want = O.block_update(W, Vf, C, alpha=-1.0, beta=2.0)
+    if dt == "bf16":
+        want = O.round_bf16(want)
+    assert np.array_equal(host(Wd), want)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n,nblk,b", [(10007, 12, 4), (3001, 6, 8), (2048, 3, 16)])
+def test_update_normal(fe, dt, n, nblk, b):
+    Vd = dev(S.normal((nblk, n, b), seed=9), DT[dt])
+    Wd = dev(S.normal((n, b), seed=10), DT[dt])
+    C = S.normal((nblk * b, b), seed=11)
+    V, W = host(Vd), host(Wd)
+    Vf = V.transpose(1, 0, 2).reshape(n, nblk * b)
+    want = O.block_update(W, Vf, C, alpha=-0.5, beta=1.0)
+    mag = np.abs(W) + 0.5 * (np.abs(Vf) @ np.abs(C))
+    fe.fe_block_update(Wd, Vd, dev(C, torch.float64), alpha=-0.5, beta=1.0)
+    got = host(Wd)
+    assert np.all(np.abs(got - want) <= ULP[dt] * np.abs(want) + 1e-13 * mag + 1e-300)
+
+
+def test_update_in_place_right_multiply(fe):
+    n, b = 5000, 4
+    W = S.normal((n, b), seed=12)
+    M = np.triu(S.normal((b, b), seed=13)) + 3 * np.eye(b)
+    Wd = dev(W, torch.float64)
+    fe.fe_block_update(Wd, Wd, dev(M, torch.float64), alpha=1.0, beta=0.0)
+    assert np.allclose(host(Wd), W @ M, rtol=1e-14, atol=1e-13)
+
+
+def test_update_beta_zero_ignores_nan(fe):
+    n, b = 100, 4
+    W = torch.full((n, b), float("nan"), dtype=torch.float32, device="cuda")
+    V = dev(S.normal((1, n, b), seed=1), torch.float32)
+    C = dev(np.eye(b), torch.float64)
+    fe.fe_block_update(W, V, C, alpha=1.0, beta=0.0)
+    assert torch.equal(W, V[0])
+
+
+def test_update_rejects_overlap(fe):
+    V = torch.zeros((3, 100, 4), dtype=torch.float32, device="cuda")
+    C = torch.zeros((12, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(fe.FeError) as e:
+        fe.fe_block_update(V[1], V, C)
+    assert e.value.status == fe.FE_EINVAL

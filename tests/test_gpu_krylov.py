@@ -1,0 +1,131 @@
+"""fe_krylov_schur on the GPU against the FP64 oracle and closed-form spectra.
+
+Bars: FP64 storage: eigenvalues within 1e-10 relative of the oracle's (same
+start block, same refill draws) and the same number of sparse products;
+FP32 storage (tol 1e-6): eigenvalues within 1e-8 relative of the FP64
+oracle, explicit FP64 residuals <= 1e-6; every returned vector satisfies
+||A x - theta x|| / |theta| <= the reported residual (checked on the CPU).
+"""
+import numpy as np
+import pytest
+import torch
+
+import fe_synth as S
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def setup(fe, g, relabel=True):
+    n, s, d = g
+    flags = fe.FE_GRAPH_DEFAULT | (fe.FE_RELABEL_BY_DEGREE if relabel else 0)
+    A = fe.fe_csr_build(n, s, d, flags)
+    rp, ci = O.csr_from_edges(n, s, d)
+    return A, rp, ci
+
+
+def oracle_ks(rp, ci, n, nev, b, m, tol, X0, **kw):
+    return O.krylov_schur(lambda X: O.spmm(rp, ci, X, threads=8), n, nev, b, m, tol, X0, **kw)
+
+
+def check_vectors(rp, ci, r, slack=10.0):
+    X = r.evecs.double().cpu().numpy()
+    AX = O.spmm(rp, ci, X)
+    res = np.linalg.norm(AX - X * r.evals, axis=0) / (O.ritz_scale(r.evals) * np.linalg.norm(X, axis=0))
+    assert np.all(res <= slack * r.resid + 1e-6 * (r.evecs.dtype != torch.float64) + 1e-13)
+
+
+def test_tiny_config_fp64_matches_oracle(fe):
+    """Chung-Lu n=65,536, Pareto 2.1, mean 16; nev=8, block 4, m=32, tol 1e-8, FP64."""
+    g = S.chung_lu_edges(65536, alpha=2.1, mean_deg=16, seed=1)
+    A, rp, ci = setup(fe, g)
+    n = A.n
+    X0 = S.normal((n, 4), seed=3)
+    ref = oracle_ks(rp, ci, n, 8, 4, 32, 1e-8, X0)
+    r = fe.fe_krylov_schur(A, 8, 4, 32, 1e-8, dtype=torch.float64,
+                           start=torch.tensor(X0, device="cuda"))
+    assert r.status == fe.FE_OK and ref.converged
+    assert np.allclose(r.evals, ref.evals, rtol=1e-10, atol=0)
+    assert r.spmm_calls == ref.spmm_calls and r.restarts == ref.restarts
+    assert r.resid.max() <= 1e-7
+    check_vectors(rp, ci, r)
+
+
+CLOSED = {
+    "complete40": (S.complete_graph(40), np.array([39.0] + [-1.0] * 39), 5, 4, 24),
+    "cycle48": (S.cycle_graph(48), 2 * np.cos(2 * np.pi * np.arange(48) / 48), 6, 4, 24),
+    "path48": (S.path_graph(48), 2 * np.cos(np.pi * np.arange(1, 49) / 49), 6, 4, 24),
+    "star40k": (S.star_graph(40000), np.array([np.sqrt(39999), -np.sqrt(39999)]), 2, 4, 24),
+}
+
+
+@pytest.mark.parametrize("name", list(CLOSED))
+@pytest.mark.parametrize("relabel", [False, True])
+def test_closed_forms_fp64(fe, name, relabel):
+    g, lam, nev, b, m = CLOSED[name]
+    A, rp, ci = setup(fe, g, relabel)
+    X0 = S.normal((A.n, b), seed=3)
+    r = fe.fe_krylov_schur(A, nev, b, m, 1e-10, dtype=torch.float64,
+                           start=torch.tensor(X0, device="cuda"))
+    assert r.status == fe.FE_OK
+    order = np.lexsort((-lam, -np.abs(lam)))
+    want = np.sort(np.abs(lam[order][:nev]))
+    assert np.allclose(np.sort(np.abs(r.evals)), want, atol=1e-9)
+    assert all(np.min(np.abs(lam - t)) < 1e-9 for t in r.evals)
+    ref = oracle_ks(rp, ci, A.n, nev, b, m, 1e-10, X0)
+    assert r.refills == ref.refills
+    check_vectors(rp, ci, r)
+
+
+def test_hypercube_fp64(fe):
+    from math import comb
+    g = S.hypercube(8)
+    lam = np.array(sum(([8 - 2 * k] * comb(8, k) for k in range(9)), []), float)
+    A, rp, ci = setup(fe, g)
+    r = fe.fe_krylov_schur(A, 6, 4, 32, 1e-10, dtype=torch.float64, seed=11)
+    assert r.status == fe.FE_OK
+    assert all(np.min(np.abs(lam - t)) < 1e-9 for t in r.evals)
+    assert np.allclose(sorted(np.abs(r.evals)), [6, 6, 6, 6, 8, 8], atol=1e-9)
+
+
+@pytest.mark.parametrize("relabel", [False, True])
+def test_rmat_fp32_vs_fp64_oracle(fe, relabel):
+    g = S.rmat_edges(14, seed=14)
+    A, rp, ci = setup(fe, g, relabel)
+    n = A.n
+    X0 = S.normal((n, 4), seed=3)
+    ref = oracle_ks(rp, ci, n, 8, 4, 48, 1e-12, X0)
+    r = fe.fe_krylov_schur(A, 8, 4, 48, 1e-6, dtype=torch.float32,
+                           start=torch.tensor(X0, dtype=torch.float32, device="cuda"))
+    assert r.status == fe.FE_OK
+    assert np.all(np.abs(r.evals - ref.evals) <= 1e-8 * np.abs(ref.evals))
+    assert r.resid.max() <= 1e-6
+    check_vectors(rp, ci, r)
+
+
+def test_rmat_bf16_storage(fe):
+    g = S.rmat_edges(13, seed=13)
+    A, rp, ci = setup(fe, g)
+    ref = oracle_ks(rp, ci, A.n, 8, 8, 64, 1e-12, S.normal((A.n, 8), seed=3))
+    r = fe.fe_krylov_schur(A, 8, 8, 64, 1e-2, dtype=torch.bfloat16, seed=5, max_restarts=200)
+    assert r.status in (fe.FE_OK, fe.FE_ENOCONV)
+    assert np.all(np.abs(r.evals - ref.evals) <= 1e-3 * np.abs(ref.evals))
+
+
+def test_random_start_deterministic(fe):
+    g = S.chung_lu_edges(20000, alpha=2.3, mean_deg=12, seed=9)
+    A, rp, ci = setup(fe, g)
+    r1 = fe.fe_krylov_schur(A, 8, 4, 32, 1e-8, dtype=torch.float32, seed=77)
+    r2 = fe.fe_krylov_schur(A, 8, 4, 32, 1e-8, dtype=torch.float32, seed=77)
+    assert np.array_equal(r1.evals, r2.evals) and r1.spmm_calls == r2.spmm_calls
+
+
+def test_no_convergence_and_bad_args(fe):
+    g = S.rmat_edges(12, seed=1)
+    A, rp, ci = setup(fe, g)
+    r = fe.fe_krylov_schur(A, 8, 4, 32, 1e-14, dtype=torch.float32, seed=1, max_restarts=1)
+    assert r.status == fe.FE_ENOCONV and r.restarts == 1 and np.all(np.isfinite(r.evals))
+    for args in [(8, 4, 30), (30, 4, 32), (8, 3, 33)]:
+        with pytest.raises(fe.FeError) as e:
+            fe.fe_krylov_schur(A, *args, 1e-8)
+        assert e.value.status in (fe.FE_EINVAL, fe.FE_EUNSUPPORTED)
