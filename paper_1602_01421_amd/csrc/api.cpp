@@ -96,13 +96,13 @@ static void free_device(Csr* A) {
   hipFree(A->d_order);
   hipFree(A->d_perm);
   hipFree(A->d_chunks);
-  hipFree(A->d_counters);
+  hipFree(A->d_first_chunk);
   hipFree(A->d_partials);
   A->d_row_ptr = nullptr;
   A->d_col = nullptr;
   A->d_order = A->d_perm = nullptr;
   A->d_chunks = nullptr;
-  A->d_counters = nullptr;
+  A->d_first_chunk = nullptr;
   A->d_partials = nullptr;
 }
 
@@ -167,11 +167,13 @@ fe_status csr_upload(Csr* A, std::vector<int64_t>&& row_ptr, std::vector<int32_t
   // hub chunks: positions [0, n_split) in degree order
   const int64_t n_split = rows_deg_gt(*A, kSplitThreshold);
   std::vector<SplitChunk> chunks;
+  std::vector<int64_t> first_chunk;
   for (int64_t pos = 0; pos < n_split; ++pos) {
     const int64_t row = relabel ? pos : order[pos];
     const int64_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
     const int32_t cnt = (int32_t)((e1 - e0 + kSplitChunk - 1) / kSplitChunk);
     const int32_t first = (int32_t)chunks.size();
+    first_chunk.push_back(first);
     for (int32_t c = 0; c < cnt; ++c) {
       SplitChunk s;
       s.e0 = e0 + c * kSplitChunk;
@@ -196,13 +198,9 @@ fe_status csr_upload(Csr* A, std::vector<int64_t>&& row_ptr, std::vector<int32_t
   }
   if (A->n_chunks) {
     if ((st = upload(&A->d_chunks, chunks.data(), chunks.size())) != FE_OK) goto err;
-    if (hipMalloc((void**)&A->d_counters, sizeof(int32_t) * n_split) != hipSuccess ||
-        hipMalloc(&A->d_partials, sizeof(double) * 64 * A->n_chunks) != hipSuccess) {
-      st = fail(FE_ENOMEM, "hipMalloc for hub scratch failed");
-      goto err;
-    }
-    if (hipMemset(A->d_counters, 0, sizeof(int32_t) * n_split) != hipSuccess) {
-      st = fail(FE_EDEVICE, "hipMemset failed");
+    if ((st = upload(&A->d_first_chunk, first_chunk.data(), first_chunk.size())) != FE_OK) goto err;
+    if (hipMalloc(&A->d_partials, sizeof(double) * 64 * A->n_chunks) != hipSuccess) {
+      st = fail(FE_ENOMEM, "hipMalloc for hub partials failed");
       goto err;
     }
   }

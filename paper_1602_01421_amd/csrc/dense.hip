@@ -70,18 +70,24 @@ __global__ __launch_bounds__(kGramWG) void gram_kernel(const T* __restrict__ V, 
   const int64_t r_end = min(n, r_begin + rows_per_wg);
   for (int64_t r0 = r_begin + wave * kGramRowsPerIter; r0 < r_end;
        r0 += (kGramWG / 64) * kGramRowsPerIter) {
+    // Unconditional loads from clamped (always valid) addresses, masked after
+    // the fact: a guarded load would serialise on its own wait.
     double a[4][kGramPG], bb[4][NQG];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t row = r0 + 4 * u + kk;
       const bool rv = row < r_end;
-      const int64_t rb = row * b;
+      const int64_t rb = (rv ? row : r_end - 1) * b;
 #pragma unroll
-      for (int pg = 0; pg < kGramPG; ++pg)
-        a[u][pg] = (rv && aval[pg]) ? load_f64(V + aoff[pg] + rb) : 0.0;
+      for (int pg = 0; pg < kGramPG; ++pg) {
+        const double x = load_f64(V + aoff[pg] + rb);
+        a[u][pg] = (rv && aval[pg]) ? x : 0.0;
+      }
 #pragma unroll
-      for (int qg = 0; qg < NQG; ++qg)
-        bb[u][qg] = (rv && bval[qg]) ? load_f64(W + rb + boff[qg]) : 0.0;
+      for (int qg = 0; qg < NQG; ++qg) {
+        const double x = load_f64(W + rb + boff[qg]);
+        bb[u][qg] = (rv && bval[qg]) ? x : 0.0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -274,6 +280,7 @@ __global__ __launch_bounds__(256) void rotate_kernel(TO* Out, int32_t out_mode,
                                                      int32_t c_out, int64_t n, const T* V,
                                                      int32_t nblk, int64_t stride,
                                                      const double* __restrict__ Y, int32_t p) {
+  using A = typename Acc<T>::type;
   extern __shared__ double Ys[];
   const int m = nblk * B;
   for (int i = threadIdx.x; i < m * p; i += blockDim.x) Ys[i] = Y[i];
@@ -281,40 +288,52 @@ __global__ __launch_bounds__(256) void rotate_kernel(TO* Out, int32_t out_mode,
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   constexpr int VEC = (B * sizeof(T) >= 16) ? 16 / sizeof(T) : B;
-  double acc[kRotMax];
+  constexpr int NB = kRotMax / B;
+  // the row's m inputs, read once (all reads precede any write of the row)
+  A v[kRotMax];
 #pragma unroll
-  for (int o = 0; o < kRotMax; ++o) acc[o] = 0.0;
-  for (int jb = 0; jb < nblk; ++jb) {
-    const T* vp = V + jb * stride + r * B;
+  for (int jb = 0; jb < NB; ++jb) {
+    if (jb < nblk) {
+      const T* vp = V + jb * stride + r * B;
 #pragma unroll
-    for (int c0 = 0; c0 < B; c0 += VEC) {
-      double tmp[VEC];
-      load_vec<T, VEC>(vp + c0, tmp);
+      for (int c0 = 0; c0 < B; c0 += VEC) load_vec<T, VEC>(vp + c0, v + jb * B + c0);
+    } else {
 #pragma unroll
-      for (int c = 0; c < VEC; ++c) {
-        const double* yr = Ys + (jb * B + c0 + c) * p;
-#pragma unroll
-        for (int o = 0; o < kRotMax; ++o)
-          if (o < p) acc[o] = fma(tmp[c], yr[o], acc[o]);
-      }
+      for (int c = 0; c < B; ++c) v[jb * B + c] = 0;
     }
   }
   if constexpr (sizeof(TO) == sizeof(T)) {
     if (out_mode == 0) {  // back into the first p/B blocks of V
 #pragma unroll
-      for (int ob = 0; ob < kRotMax / B; ++ob)
+      for (int ob = 0; ob < NB; ++ob) {
         if (ob * B < p) {
+          double acc[B];
+#pragma unroll
+          for (int q = 0; q < B; ++q) acc[q] = 0.0;
+#pragma unroll
+          for (int t = 0; t < kRotMax; ++t) {
+            if (t < m) {
+              const double* yr = Ys + t * p + ob * B;
+#pragma unroll
+              for (int q = 0; q < B; ++q) acc[q] = fma((double)v[t], yr[q], acc[q]);
+            }
+          }
 #pragma unroll
           for (int c0 = 0; c0 < B; c0 += VEC)
-            store_vec<TO, VEC>(Out + ob * stride + r * B + c0, acc + ob * B + c0);
+            store_vec<TO, VEC>(Out + ob * stride + r * B + c0, acc + c0);
         }
+      }
       return;
     }
   }
   // packed n x c_out
+  for (int o = 0; o < c_out; ++o) {
+    double acc = 0.0;
 #pragma unroll
-  for (int o = 0; o < kRotMax; ++o)
-    if (o < c_out) Out[r * c_out + o] = to_storage<TO, double>(acc[o]);
+    for (int t = 0; t < kRotMax; ++t)
+      if (t < m) acc = fma((double)v[t], Ys[t * p + o], acc);
+    Out[r * c_out + o] = to_storage<TO, double>(acc);
+  }
 }
 
 template <typename T, typename TO = T>
@@ -364,14 +383,15 @@ __global__ __launch_bounds__(256) void resid_kernel(const double* __restrict__ A
     }
     for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (i0 + u < c) {
-          const double x = X[r * c + i0 + u], ax = AX[r * c + i0 + u];
-          const double d = ax - th[u] * x;
-          s0[u] = fma(x, ax, s0[u]);
-          s1[u] = fma(x, x, s1[u]);
-          s2[u] = fma(d, d, s2[u]);
-        }
+      for (int u = 0; u < 8; ++u) {
+        const int64_t e = r * c + (i0 + u < c ? i0 + u : c - 1);  // clamped, masked below
+        const double xr = X[e], axr = AX[e];
+        const double x = (i0 + u < c) ? xr : 0.0, ax = (i0 + u < c) ? axr : 0.0;
+        const double d = ax - th[u] * x;
+        s0[u] = fma(x, ax, s0[u]);
+        s1[u] = fma(x, x, s1[u]);
+        s2[u] = fma(d, d, s2[u]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u)

@@ -35,15 +35,15 @@ inline bool dtype_ok(fe_dtype dt) { return dt == FE_F64 || dt == FE_F32 || dt ==
 
 // ------------------------------------------------------------- sparse side
 // Rows with more nonzeros than kSplitThreshold are cut into chunks of
-// kSplitChunk nonzeros, one workgroup each, combined by the last workgroup
-// to finish (deterministic order).
+// kSplitChunk nonzeros, one workgroup each; a second launch adds the chunk
+// partials of each row in chunk order (deterministic).
 constexpr int64_t kSplitThreshold = 16384;
 constexpr int64_t kSplitChunk = 8192;
 constexpr int64_t kBlockThreshold = 2048;  // rows above this get a whole workgroup
 
 struct SplitChunk {
   int64_t e0, e1;    // nonzero range of this chunk
-  int32_t pos;       // position of the row in degree order (== counter index)
+  int32_t pos;       // position of the row in degree order
   int32_t first;     // index of the row's first chunk
   int32_t count;     // chunks of this row
   int32_t pad;
@@ -63,8 +63,8 @@ struct Csr {
   // split rows
   int64_t n_split_rows = 0, n_chunks = 0;
   SplitChunk* d_chunks = nullptr;
-  int32_t* d_counters = nullptr;  // n_split_rows, zero between calls
-  void* d_partials = nullptr;     // n_chunks * 64 doubles
+  int64_t* d_first_chunk = nullptr;  // n_split_rows: index of each hub row's first chunk
+  void* d_partials = nullptr;        // n_chunks * 64 doubles
 };
 
 // number of rows with degree > t for t = 0 or a power of two

@@ -9,9 +9,9 @@
 // and cut into bins; ONE launch covers every bin, the workgroup index picking
 // its bin from a small prefix table, heaviest bins first so long workgroups
 // start early:
-//   split  : degree > 16384 -> chunks of 8192 nonzeros, one workgroup each;
-//            the last workgroup of a row (device-scope counter) adds the
-//            per-chunk partials in chunk order, so results are deterministic
+//   split  : degree > 16384 -> chunks of 8192 nonzeros, one workgroup each,
+//            writing partial sums; a second small launch adds each row's
+//            partials in chunk order, so results are deterministic
 //   block  : 2048 < degree <= 16384 -> one 256-lane workgroup per row, LDS
 //            reduction across its four wavefronts
 //   group  : smaller rows -> groups of E*CPAD lanes per row inside a 64-wide
@@ -30,7 +30,7 @@
 namespace fe {
 namespace {
 
-enum Kind : int32_t { K_ZERO = 0, K_GROUP = 1, K_BLOCK = 2, K_SPLIT = 3 };
+enum Kind : int32_t { K_ZERO = 0, K_GROUP = 1, K_BLOCK = 2, K_SPLIT = 3, K_WAVE = 4 };
 constexpr int kMaxBins = 16;
 constexpr int kWG = 256;
 
@@ -47,39 +47,40 @@ struct Plan {
   const int32_t* col;
   const int32_t* order;  // null: position == row
   const SplitChunk* chunks;
-  int32_t* counters;
   void* partials;
   int32_t b;
   int32_t nbins;
   Bin bins[kMaxBins];
 };
 
-template <typename T, int VEC, int CPAD, int SLOTS, typename A>
+// Sum the X rows named by col[e], col[e + SLOTS], ... (< e1) into acc.  Each
+// pass issues U index loads and then U gathers per lane before consuming any
+// of them, so a whole row's traffic is in flight at once.  Out-of-range slots
+// re-read the row's last index (a cache hit) and contribute zero, which keeps
+// the loop free of divergent branches.
+template <typename T, int VEC, int CPAD, int SLOTS, int U, typename A>
 __device__ __forceinline__ void gather_rows(const Plan& P, const T* __restrict__ X, int64_t e,
                                             int64_t e1, int chunk, bool live, A* acc) {
   const int32_t* __restrict__ col = P.col;
   const int64_t b = P.b;
   const T* Xc = X + chunk * VEC;
   if (!live) return;
-  for (; e + 3 * SLOTS < e1; e += 4 * SLOTS) {
-    int32_t j0 = __builtin_nontemporal_load(col + e);
-    int32_t j1 = __builtin_nontemporal_load(col + e + SLOTS);
-    int32_t j2 = __builtin_nontemporal_load(col + e + 2 * SLOTS);
-    int32_t j3 = __builtin_nontemporal_load(col + e + 3 * SLOTS);
-    A v0[VEC], v1[VEC], v2[VEC], v3[VEC];
-    load_vec<T, VEC>(Xc + j0 * b, v0);
-    load_vec<T, VEC>(Xc + j1 * b, v1);
-    load_vec<T, VEC>(Xc + j2 * b, v2);
-    load_vec<T, VEC>(Xc + j3 * b, v3);
+  for (; e < e1; e += U * SLOTS) {
+    int32_t j[U];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) acc[v] += (v0[v] + v1[v]) + (v2[v] + v3[v]);
-  }
-  for (; e < e1; e += SLOTS) {
-    int32_t j = __builtin_nontemporal_load(col + e);
-    A v0[VEC];
-    load_vec<T, VEC>(Xc + j * b, v0);
+    for (int u = 0; u < U; ++u) {
+      const int64_t idx = e + u * SLOTS;
+      j[u] = __builtin_nontemporal_load(col + (idx < e1 ? idx : e1 - 1));
+    }
+    A v[U][VEC];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) acc[v] += v0[v];
+    for (int u = 0; u < U; ++u) load_vec<T, VEC>(Xc + j[u] * b, v[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = e + u * SLOTS < e1;
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) acc[c] += ok ? v[u][c] : (A)0;
+    }
   }
 }
 
@@ -93,7 +94,7 @@ __device__ __forceinline__ void reduce_slots(A* acc) {
   }
 }
 
-template <typename T, int VEC, int CPAD, int E>
+template <typename T, int VEC, int CPAD, int E, int U>
 __device__ __forceinline__ void run_group(const Plan& P, const Bin& B, int64_t local, const T* __restrict__ X,
                           T* __restrict__ Y) {
   using A = typename Acc<T>::type;
@@ -111,7 +112,7 @@ __device__ __forceinline__ void run_group(const Plan& P, const Bin& B, int64_t l
   A acc[VEC];
 #pragma unroll
   for (int v = 0; v < VEC; ++v) acc[v] = 0;
-  gather_rows<T, VEC, CPAD, E>(P, X, e0 + slot, e1, chunk, live, acc);
+  gather_rows<T, VEC, CPAD, E, U>(P, X, e0 + slot, e1, chunk, live, acc);
   reduce_slots<E, CPAD, A, VEC>(acc);
   if (slot == 0 && live) store_vec_nt<T, VEC>(Y + row * P.b + chunk * VEC, acc);
 }
@@ -129,7 +130,7 @@ __device__ __forceinline__ void run_wg_range(const Plan& P, const T* __restrict_
   const bool live = chunk * VEC < P.b;
 #pragma unroll
   for (int v = 0; v < VEC; ++v) acc[v] = 0;
-  gather_rows<T, VEC, CPAD, SLOTS>(P, X, e0 + slot, e1, chunk, live, acc);
+  gather_rows<T, VEC, CPAD, SLOTS, 8>(P, X, e0 + slot, e1, chunk, live, acc);
   reduce_slots<64 / CPAD, CPAD, A, VEC>(acc);
   const int w = t >> 6, l = t & 63;
   if (l < CPAD) {
@@ -157,11 +158,14 @@ __device__ __forceinline__ void run_block(const Plan& P, const Bin& B, int64_t l
   if (t < CPAD && t * VEC < P.b) store_vec_nt<T, VEC>(Y + row * P.b + t * VEC, acc);
 }
 
+// A chunk of a hub row: its partial sum goes to the partials buffer; the
+// combine kernel adds a row's partials in chunk order after this launch
+// (stream order makes them visible without device-scope fences, which write
+// back the L2 of every XCD on this part).
 template <typename T, int VEC, int CPAD>
-__device__ __forceinline__ void run_split(const Plan& P, const Bin& B, int64_t local, const T* __restrict__ X,
-                          T* __restrict__ Y) {
+__device__ __forceinline__ void run_split(const Plan& P, const Bin& B, int64_t local,
+                                          const T* __restrict__ X) {
   using A = typename Acc<T>::type;
-  __shared__ int last;
   const int64_t ci = B.pos0 + local;
   const SplitChunk c = P.chunks[ci];
   A acc[VEC];
@@ -172,25 +176,6 @@ __device__ __forceinline__ void run_split(const Plan& P, const Bin& B, int64_t l
 #pragma unroll
     for (int v = 0; v < VEC; ++v) part[ci * P.b + t * VEC + v] = acc[v];
   }
-  __threadfence();
-  __syncthreads();
-  if (t == 0) last = (atomicAdd(P.counters + c.pos, 1) == c.count - 1);
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  if (t < CPAD && t * VEC < P.b) {
-    A s[VEC];
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) s[v] = 0;
-    for (int32_t i = 0; i < c.count; ++i) {
-      const A* q = part + (int64_t)(c.first + i) * P.b + t * VEC;
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) s[v] += __builtin_nontemporal_load(q + v);
-    }
-    const int64_t row = P.order ? (int64_t)P.order[c.pos] : (int64_t)c.pos;
-    store_vec_nt<T, VEC>(Y + row * P.b + t * VEC, s);
-  }
-  if (t == 0) P.counters[c.pos] = 0;  // ready for the next call
 }
 
 template <typename T, int VEC, int CPAD>
@@ -223,7 +208,7 @@ __global__ __launch_bounds__(kWG) void spmm_kernel(Plan P, const T* __restrict__
   const int64_t local = wg - B.wg0;
   switch (B.kind) {
     case K_SPLIT:
-      run_split<T, VEC, CPAD>(P, B, local, X, Y);
+      run_split<T, VEC, CPAD>(P, B, local, X);
       break;
     case K_BLOCK:
       run_block<T, VEC, CPAD>(P, B, local, X, Y);
@@ -231,16 +216,38 @@ __global__ __launch_bounds__(kWG) void spmm_kernel(Plan P, const T* __restrict__
     case K_ZERO:
       run_zero<T, VEC, CPAD>(P, B, local, Y);
       break;
-    default:
+    case K_WAVE:  // one wavefront (64 / CPAD slots) per row, long rows
+      run_group<T, VEC, CPAD, 64 / CPAD, 8>(P, B, local, X, Y);
+      break;
+    default:  // short rows: E slots, at most two nonzeros per slot
       switch (B.E) {
-        case 1: run_group<T, VEC, CPAD, 1>(P, B, local, X, Y); break;
-        case 2: if constexpr (2 * CPAD <= 64) run_group<T, VEC, CPAD, 2>(P, B, local, X, Y); break;
-        case 4: if constexpr (4 * CPAD <= 64) run_group<T, VEC, CPAD, 4>(P, B, local, X, Y); break;
-        case 8: if constexpr (8 * CPAD <= 64) run_group<T, VEC, CPAD, 8>(P, B, local, X, Y); break;
-        case 16: if constexpr (16 * CPAD <= 64) run_group<T, VEC, CPAD, 16>(P, B, local, X, Y); break;
-        case 32: if constexpr (32 * CPAD <= 64) run_group<T, VEC, CPAD, 32>(P, B, local, X, Y); break;
-        case 64: if constexpr (64 * CPAD <= 64) run_group<T, VEC, CPAD, 64>(P, B, local, X, Y); break;
+        case 1: run_group<T, VEC, CPAD, 1, 2>(P, B, local, X, Y); break;
+        case 2: if constexpr (2 * CPAD <= 64) run_group<T, VEC, CPAD, 2, 2>(P, B, local, X, Y); break;
+        case 4: if constexpr (4 * CPAD <= 64) run_group<T, VEC, CPAD, 4, 2>(P, B, local, X, Y); break;
+        case 8: if constexpr (8 * CPAD <= 64) run_group<T, VEC, CPAD, 8, 2>(P, B, local, X, Y); break;
+        case 16: if constexpr (16 * CPAD <= 64) run_group<T, VEC, CPAD, 16, 2>(P, B, local, X, Y); break;
+        case 32: if constexpr (32 * CPAD <= 64) run_group<T, VEC, CPAD, 32, 2>(P, B, local, X, Y); break;
       }
+  }
+}
+
+// Y row of hub `pos` = sum of its chunk partials, in chunk order.
+template <typename T>
+__global__ __launch_bounds__(64) void split_combine_kernel(const SplitChunk* __restrict__ chunks,
+                                                           const int64_t* __restrict__ first_chunk,
+                                                           const int32_t* __restrict__ order,
+                                                           const void* __restrict__ partials,
+                                                           int32_t b, T* __restrict__ Y) {
+  using A = typename Acc<T>::type;
+  const int64_t pos = blockIdx.x;
+  const int64_t f = first_chunk[pos];
+  const int32_t cnt = chunks[f].count;
+  const A* part = reinterpret_cast<const A*>(partials);
+  const int64_t row = order ? (int64_t)order[pos] : pos;
+  for (int c = threadIdx.x; c < b; c += 64) {
+    A s = 0;
+    for (int32_t i = 0; i < cnt; ++i) s += part[(f + i) * b + c];
+    Y[row * b + c] = to_storage<T, A>(s);
   }
 }
 
@@ -260,7 +267,6 @@ fe_status make_plan(const Csr& A, int32_t b, int cpad, int vec, Plan* P, int64_t
   P->col = A.d_col;
   P->order = A.d_order;
   P->chunks = A.d_chunks;
-  P->counters = A.d_counters;
   P->partials = A.d_partials;
   P->b = b;
   int nb = 0;
@@ -286,7 +292,7 @@ fe_status make_plan(const Csr& A, int32_t b, int cpad, int vec, Plan* P, int64_t
   add(K_BLOCK, 0, c_split, c_block - c_split, 1);
   // wave-size groups: ecap < deg <= kBlockThreshold
   const int64_t c_ecap = rows_deg_gt(A, ecap);
-  add(K_GROUP, ecap, c_block, c_ecap - c_block, kWG / (ecap * cpad));
+  add(K_WAVE, ecap, c_block, c_ecap - c_block, kWG / (ecap * cpad));
   // group bins: deg in (2^(g-1), 2^g] with E = 2^(g-1) < ecap, then deg == 1 with E = 1
   int64_t hi_pos = c_ecap;
   for (int g = ilog2_floor(ecap); g >= 1; --g) {
@@ -316,6 +322,12 @@ fe_status launch_t(const Csr& A, const void* X, void* Y, int32_t b, hipStream_t 
   hipLaunchKernelGGL((spmm_kernel<T, VEC, CPAD>), dim3((uint32_t)wg), dim3(kWG), 0, s, P,
                      static_cast<const T*>(X), static_cast<T*>(Y));
   FE_HIP(hipGetLastError());
+  if (A.n_split_rows > 0) {
+    hipLaunchKernelGGL((split_combine_kernel<T>), dim3((uint32_t)A.n_split_rows), dim3(64), 0, s,
+                       A.d_chunks, A.d_first_chunk, A.d_order, A.d_partials, b,
+                       static_cast<T*>(Y));
+    FE_HIP(hipGetLastError());
+  }
   return FE_OK;
 }
 
