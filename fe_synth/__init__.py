@@ -174,3 +174,36 @@ def hypercube(d: int):
         src.append(v[keep])
         dst.append(u[keep])
     return _pairs(np.concatenate(src), np.concatenate(dst), n)
+
+
+# ----------------------------------------------------- learned-start graph set
+
+def learned_start_graph(seed: int, min_log2n: int = 14, max_log2n: int = 18):
+    """One graph of the learned-start training/evaluation family.
+
+    With equal odds: Chung-Lu with Pareto exponent alpha ~ U[2.0, 2.8], or a
+    stochastic block model with k ~ U{4..16} equal blocks and in-block
+    fraction rho ~ U[0.6, 0.9]; n = 2^U{min_log2n..max_log2n}; target mean
+    degree ~ U[8, 32].  The recipe is drawn from numpy's PCG64 seeded with
+    `seed`; the edges from Philox with the same seed.  Returns
+    (n, src, dst, description).
+    """
+    rng = np.random.default_rng(seed)
+    kind = "chung_lu" if rng.random() < 0.5 else "sbm"
+    n = 1 << int(rng.integers(min_log2n, max_log2n + 1))
+    mean = float(rng.uniform(8.0, 32.0))
+    if kind == "chung_lu":
+        alpha = float(rng.uniform(2.0, 2.8))
+        n, s, d = chung_lu_edges(n, alpha=alpha, mean_deg=mean, seed=seed)
+        desc = f"chung_lu n={n} alpha={alpha:.2f} mean={mean:.1f}"
+    else:
+        k = int(rng.integers(4, 17))
+        rho = float(rng.uniform(0.6, 0.9))
+        n, s, d = sbm_edges(n, k, rho, mean, seed=seed)
+        desc = f"sbm n={n} k={k} rho={rho:.2f} mean={mean:.1f}"
+    return n, s, d, desc
+
+
+def learned_start_features(n: int, seed: int) -> np.ndarray:
+    """The network's per-vertex random inputs: (n, 15) N(0,1) draws (stream 7)."""
+    return normal((n, 15), seed=seed, stream=7)

@@ -205,6 +205,49 @@ fe_status fe_krylov_schur(const fe_csr *A, int32_t nev, int32_t block, int32_t m
                           const fe_ks_opts *opts, double *evals, void *evecs,
                           fe_ks_report *rep);
 
+/* ------------------------------------------------------------------------
+ * Learned start block (not in the paper; the learned warm start of this
+ * build).  A three-layer graph network over Ahat = D^-1/2 A D^-1/2:
+ *   h0_i = [log(1 + deg_i), z_i (15 values)]
+ *   S_l = Ahat H_{l-1};  H_l = relu(S_l W_l + H_{l-1} U_l + b_l)   (hidden 64)
+ *   X = H_3 P                                                      (8 columns)
+ * Parameters live on the device as FP32 masters (flattened in the order
+ * W0 U0 b0 W1 U1 b1 W2 U2 b2 P, matrices row-major, 19,136 floats); the dense
+ * transforms run on BF16 MFMA with FP32 accumulation, aggregation on fe_spmm
+ * in FP32.  z, V and X are device FP32 blocks in the ORIGINAL vertex order
+ * (the library permutes for relabelled handles).  Loss against eigenvectors
+ * V (n x 8, orthonormal): L = 1 - ||V^T Q||_F^2 / 8 with Q an orthonormal
+ * basis of span(X).
+ * ---------------------------------------------------------------------- */
+typedef struct fe_gnn fe_gnn;
+
+/* Number of parameters (19,136). */
+int64_t fe_gnn_param_count(void);
+
+/* New network with Glorot-uniform weights drawn from Philox(seed), zero
+   biases and a fresh Adam state.  Errors: FE_EINVAL (NULL), FE_ENOMEM. */
+fe_status fe_gnn_create(uint64_t seed, fe_gnn **out);
+void fe_gnn_free(fe_gnn *g);
+
+/* Host copies of the FP32 parameters in the flattened order.  set also
+   clears the stored gradients and the Adam state. */
+fe_status fe_gnn_get_params(const fe_gnn *g, float *host);
+fe_status fe_gnn_set_params(fe_gnn *g, const float *host);
+
+/* X (device n x 8 FP32) = network output for graph A with random features z
+   (device n x 15 FP32).  Synchronises the stream.  Errors: FE_EINVAL, FE_ENOMEM, FE_EDEVICE. */
+fe_status fe_gnn_forward(fe_gnn *g, const fe_csr *A, const float *z, float *X, void *hip_stream);
+
+/* Forward, loss against V (device n x 8 FP32, orthonormal columns) and
+   backward; the gradients are kept in g (and copied to grads_host, 19,136
+   floats, when not NULL); *loss receives L.  Synchronises the stream. */
+fe_status fe_gnn_backward(fe_gnn *g, const fe_csr *A, const float *z, const float *V,
+                          double *loss, float *grads_host, void *hip_stream);
+
+/* One Adam step (Kingma & Ba: beta1 0.9, beta2 0.999, eps 1e-8, bias
+   corrected) with the gradients stored by the last fe_gnn_backward. */
+fe_status fe_gnn_adam(fe_gnn *g, double lr, void *hip_stream);
+
 /*
  * Host utility: eigendecomposition of a small dense symmetric matrix (the
  * projected problem of the eigen-iteration, which the paper solves with

@@ -23,7 +23,9 @@ FE_GRAPH_DEFAULT = FE_SYMMETRIZE | FE_DEDUPE | FE_DROP_SELF
 
 EXPORTED = ("fe_last_error", "fe_version", "fe_csr_build", "fe_csr_from_csr", "fe_csr_info",
             "fe_csr_perm", "fe_csr_export", "fe_csr_free", "fe_spmm", "fe_gram",
-            "fe_block_update", "fe_krylov_schur", "fe_dense_symeig")
+            "fe_block_update", "fe_krylov_schur", "fe_dense_symeig", "fe_gnn_param_count",
+            "fe_gnn_create", "fe_gnn_free", "fe_gnn_get_params", "fe_gnn_set_params",
+            "fe_gnn_forward", "fe_gnn_backward", "fe_gnn_adam")
 
 
 class FeError(RuntimeError):
@@ -80,6 +82,12 @@ def lib():
             "fe_krylov_schur": [P, i32, i32, i32, f64, ctypes.POINTER(KsOpts), P, P,
                                 ctypes.POINTER(KsReport)],
             "fe_dense_symeig": [i32, P, P, P],
+            "fe_gnn_create": [ctypes.c_uint64, ctypes.POINTER(P)],
+            "fe_gnn_get_params": [P, P],
+            "fe_gnn_set_params": [P, P],
+            "fe_gnn_forward": [P, P, P, P, P],
+            "fe_gnn_backward": [P, P, P, P, ctypes.POINTER(ctypes.c_double), P, P],
+            "fe_gnn_adam": [P, f64, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -87,6 +95,10 @@ def lib():
             f.restype = i32
         L.fe_csr_free.argtypes = [P]
         L.fe_csr_free.restype = None
+        L.fe_gnn_free.argtypes = [P]
+        L.fe_gnn_free.restype = None
+        L.fe_gnn_param_count.argtypes = []
+        L.fe_gnn_param_count.restype = i64
         _lib = L
     return _lib
 
@@ -303,3 +315,74 @@ def fe_dense_symeig(a: np.ndarray):
     z = np.empty((n, n))
     _check(lib().fe_dense_symeig(n, _np_ptr(a), _np_ptr(w), _np_ptr(z)))
     return w, z
+
+
+# ------------------------------------------------------------ learned start
+GNN_SHAPES = [("W0", (16, 64)), ("U0", (16, 64)), ("b0", (64,)),
+              ("W1", (64, 64)), ("U1", (64, 64)), ("b1", (64,)),
+              ("W2", (64, 64)), ("U2", (64, 64)), ("b2", (64,)), ("P", (64, 8))]
+
+
+def gnn_unflatten(flat: np.ndarray) -> dict:
+    out, at = {}, 0
+    for name, shp in GNN_SHAPES:
+        size = int(np.prod(shp))
+        out[name] = np.asarray(flat[at:at + size], dtype=np.float64).reshape(shp)
+        at += size
+    return out
+
+
+def gnn_flatten(params: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(params[name], dtype=np.float32).ravel()
+                           for name, _ in GNN_SHAPES])
+
+
+class Gnn:
+    """Owning wrapper of an fe_gnn (learned start-block network)."""
+
+    def __init__(self, seed: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().fe_gnn_create(seed, ctypes.byref(h)))
+        self._h = h
+        self.count = int(lib().fe_gnn_param_count())
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.count, dtype=np.float32)
+        _check(lib().fe_gnn_get_params(self._h, _np_ptr(out)))
+        return out
+
+    def set_params(self, flat: np.ndarray):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        assert flat.shape == (self.count,)
+        _check(lib().fe_gnn_set_params(self._h, _np_ptr(flat)))
+
+    def forward(self, A: Csr, z, X=None, stream=None):
+        """X (n x 8, original vertex order) for random features z (n x 15, FP32 device)."""
+        import torch
+        if X is None:
+            X = torch.empty((A.n, 8), dtype=torch.float32, device="cuda")
+        _check(lib().fe_gnn_forward(self._h, A.handle, _dev_ptr(z), _dev_ptr(X), _stream(stream)))
+        return X
+
+    def backward(self, A: Csr, z, V, want_grads: bool = False, stream=None):
+        """Forward + loss + backward; returns (loss, grads or None)."""
+        loss = ctypes.c_double()
+        g = np.empty(self.count, dtype=np.float32) if want_grads else None
+        _check(lib().fe_gnn_backward(self._h, A.handle, _dev_ptr(z), _dev_ptr(V),
+                                     ctypes.byref(loss), _np_ptr(g) if g is not None else None,
+                                     _stream(stream)))
+        return loss.value, g
+
+    def adam(self, lr: float = 1e-3, stream=None):
+        _check(lib().fe_gnn_adam(self._h, lr, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().fe_gnn_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,91 @@
+"""Learned-start network on the GPU against the FP64 oracle.
+
+Bars (BF16 GEMM inputs, FP32 accumulation and storage): output X within 2e-2
+relative (Frobenius, per column); loss within 1e-2 absolute; each parameter
+tensor's gradient within 5e-2 relative (Frobenius); an Adam step matches the
+oracle's Adam on the GPU's own gradients to 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+import fe_synth as S
+import oracle as O
+from oracle import gnn as G
+
+pytestmark = pytest.mark.gpu
+
+
+def case(fe, n=6000, seed=4, relabel=False):
+    n, s, d = S.chung_lu_edges(n, alpha=2.2, mean_deg=10, seed=seed)
+    flags = fe.FE_GRAPH_DEFAULT | (fe.FE_RELABEL_BY_DEGREE if relabel else 0)
+    A = fe.fe_csr_build(n, s, d, flags)
+    rp, ci = O.csr_from_edges(n, s, d)
+    z = S.normal((n, 15), seed=seed + 1)
+    V, _ = np.linalg.qr(S.normal((n, 8), seed=seed + 2))
+    return A, rp, ci, z, V
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+@pytest.mark.parametrize("relabel", [False, True])
+def test_forward_matches_oracle(fe, relabel):
+    A, rp, ci, z, V = case(fe, relabel=relabel)
+    net = fe.Gnn(seed=7)
+    params = fe.gnn_unflatten(net.get_params())
+    X = net.forward(A, torch.tensor(z, dtype=torch.float32, device="cuda")).double().cpu().numpy()
+    Xo, _ = G.forward(rp, ci, G.features(rp, z), params)
+    for j in range(8):
+        assert rel(X[:, j], Xo[:, j]) < 2e-2, j
+
+
+@pytest.mark.parametrize("relabel", [False, True])
+def test_gradients_match_oracle(fe, relabel):
+    A, rp, ci, z, V = case(fe, n=5000, seed=9, relabel=relabel)
+    net = fe.Gnn(seed=3)
+    params = fe.gnn_unflatten(net.get_params())
+    for l in range(3):  # non-zero biases exercise the bias path
+        params[f"b{l}"] = 0.05 * S.normal((64,), seed=20 + l)
+    net.set_params(fe.gnn_flatten(params))
+    loss, g = net.backward(A, torch.tensor(z, dtype=torch.float32, device="cuda"),
+                           torch.tensor(V, dtype=torch.float32, device="cuda"), want_grads=True)
+    Xo, cache = G.forward(rp, ci, G.features(rp, z), params)
+    lo = G.loss(Xo, V)
+    go = G.backward(rp, ci, params, cache, G.loss_grad(Xo, V))
+    assert abs(loss - lo) < 1e-2
+    gd = fe.gnn_unflatten(g)
+    for name in go:
+        assert rel(gd[name], go[name]) < 5e-2, (name, rel(gd[name], go[name]))
+
+
+def test_adam_step_matches_oracle(fe):
+    A, rp, ci, z, V = case(fe, n=3000, seed=11)
+    net = fe.Gnn(seed=5)
+    p0 = net.get_params().astype(np.float64)
+    zt = torch.tensor(z, dtype=torch.float32, device="cuda")
+    Vt = torch.tensor(V, dtype=torch.float32, device="cuda")
+    _, g = net.backward(A, zt, Vt, want_grads=True)
+    net.adam(1e-2)
+    torch.cuda.synchronize()
+    p1 = net.get_params().astype(np.float64)
+    st = {}
+    want = G.adam_step({"p": p0.copy()}, {"p": g.astype(np.float64)}, st, lr=1e-2)["p"]
+    assert np.allclose(p1, want, rtol=1e-5, atol=1e-7)
+
+
+def test_training_reduces_loss(fe):
+    """A few Adam steps on one graph lower the loss (sanity of the whole loop)."""
+    A, rp, ci, z, V = case(fe, n=4000, seed=13)
+    # targets: the graph's own leading eigenvectors (FP64 solver)
+    r = fe.fe_krylov_schur(A, 8, 8, 48, 1e-8, dtype=torch.float64, seed=1)
+    Vt = r.evecs.float().contiguous()
+    zt = torch.tensor(z, dtype=torch.float32, device="cuda")
+    net = fe.Gnn(seed=1)
+    l0, _ = net.backward(A, zt, Vt)
+    for _ in range(60):
+        net.backward(A, zt, Vt)
+        net.adam(3e-3)
+    l1, _ = net.backward(A, zt, Vt)
+    assert l1 < l0 - 0.05, (l0, l1)
