@@ -118,6 +118,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--block", type=int, default=4)
+    ap.add_argument("--m", type=int, default=48)
+    ap.add_argument("--mixed", action="store_true",
+                    help="BF16 storage widened to FP32 when BF16 stalls (mixed-precision solve)")
+    ap.add_argument("--sweep", default="1,2,4,8,16", help="SpMM-only widths (FP32)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--spmm-reps", type=int, default=50)
     args = ap.parse_args()
@@ -147,7 +152,7 @@ def main():
 
     # SpMM-only sweep (FP32)
     sweep = []
-    for b in (1, 2, 4, 8, 16):
+    for b in [int(x) for x in args.sweep.split(",") if x]:
         t = time_spmm(P, A, b, torch.float32, stream, args.spmm_reps)
         by = spmm_bytes(A.n, A.nnz, b, 4)
         sweep.append({"b": b, "us": t * 1e6, "gedge_col_s": A.nnz * b / t / 1e9,
@@ -156,11 +161,12 @@ def main():
             f"{by/t/1e9:7.1f} GB/s ({100*by/t/1e9/HBM_PEAK_GBS:.1f}% of HBM)")
 
     # whole-path steps: one solve each
-    nev, block, m, tol = 8, 4, 48, 1e-6
+    nev, block, m, tol = 8, args.block, args.m, 1e-6
 
     def solve(seed, profile=False):
         return P.fe_krylov_schur(A, nev, block, m, tol, dtype=torch.float32, seed=seed,
-                                 stream=stream, want_vectors=True, profile=profile)
+                                 stream=stream, want_vectors=True, profile=profile,
+                                 mixed=args.mixed)
 
     for w in range(args.warmup):
         r = solve(100 + w)
@@ -193,23 +199,28 @@ def main():
     log("profile: " + ", ".join(f"{c} {v[0]*1e3:.1f} ms / {v[2]} launches "
                                  f"({v[1]/max(v[0],1e-12)/1e9:.0f} GB/s)" for c, v in classes.items())
         + f", other {rp.t_other_dev*1e3:.1f} ms, host {rp.t_host*1e3:.1f} ms, total {rp.t_total*1e3:.1f} ms")
+    default_cfg = args.scale == 22 and block == 4 and m == 48 and not args.mixed
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(dom),
+            "traffic": measured_traffic(dom) if default_cfg else None,
             "launches": calls_dom, "avg_launch_us": t_dom / calls_dom * 1e6,
             "algorithmic_bytes_per_launch": b_dom / calls_dom}
 
     out = {
         "metric": METRIC, "value": value, "unit": "GEdge·col/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t_all / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16+f32" if args.mixed else "f32",
         "data": "synthetic",
-        "config": {"workload": f"rmat{args.scale}_krylov_schur_nev8_b4_m48_f32", "scale": args.scale,
-                   "n": A.n, "nnz": A.nnz, "edge_factor": 16, "rmat_abcd": [0.57, 0.19, 0.19, 0.05],
-                   "nev": nev, "block": block, "m": m, "tol": tol, "relabel": "degree"},
+        "config": {"workload": f"rmat{args.scale}_krylov_schur_nev8_b{block}_m{m}_"
+                               + ("mixed_bf16_f32" if args.mixed else "f32"),
+                   "scale": args.scale, "n": A.n, "nnz": A.nnz, "edge_factor": 16,
+                   "rmat_abcd": [0.57, 0.19, 0.19, 0.05], "nev": nev, "block": block, "m": m,
+                   "tol": tol, "relabel": "degree", "storage": "bf16->f32" if args.mixed else "f32"},
         "roofline": roof,
         "time_to_8_eigs_s": float(np.median(times)),
         "solve": {"restarts": [r.restarts for r in results],
+                  "spmm_calls_bf16": [r.spmm_calls_low for r in results],
                   "spmm_calls": [r.spmm_calls for r in results],
                   "max_resid": [float(r.resid.max()) for r in results],
                   "evals": [float(x) for x in results[-1].evals]},

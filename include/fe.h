@@ -158,6 +158,11 @@ typedef struct {
   double eta;            /* dependence threshold; 0 -> 1e-6 (F64), 1e-5 (F32), 3e-2 (BF16) */
   int32_t profile;       /* 1 = time each kernel class with HIP events */
   int32_t verbose;       /* 1 = print one line per restart to stderr */
+  int32_t mixed;         /* 1 = mixed-precision storage: the subspace starts in BF16
+                            and is widened to dt (FP32 or FP64) once the BF16
+                            iteration stalls or its worst residual estimate drops
+                            below mixed_switch; the Krylov state carries over */
+  double mixed_switch;   /* 0 -> 1e-3 */
 } fe_ks_opts;
 
 /* Per-solve report (all times in seconds). */
@@ -168,6 +173,8 @@ typedef struct {
   int32_t converged;       /* number of wanted pairs meeting tol at the last check */
   int32_t refills;         /* dependent columns replaced by random vectors */
   int32_t gram_calls, update_calls;
+  int32_t switch_restart;  /* restart at which a mixed solve widened its storage, -1 if never */
+  int32_t spmm_calls_low;  /* products done while the storage was BF16 (mixed solves) */
   double rho[64];          /* Krylov-Schur residual estimate / max(eps^(2/3),|theta|) per pair */
   double ritz[64];         /* Ritz values of the projected matrix at the last check */
   double resid[64];        /* explicit ||A x - q x|| / (max(eps^(2/3),|q|) ||x||), q the
@@ -225,8 +232,11 @@ typedef struct fe_gnn fe_gnn;
 int64_t fe_gnn_param_count(void);
 
 /* New network with Glorot-uniform weights drawn from Philox(seed), zero
-   biases and a fresh Adam state.  Errors: FE_EINVAL (NULL), FE_ENOMEM. */
-fe_status fe_gnn_create(uint64_t seed, fe_gnn **out);
+   biases and a fresh Adam state.  compute = FE_BF16 runs the forward
+   transforms on BF16 MFMA (BF16 copies of the FP32 weights, FP32
+   accumulation); FE_F32 runs them on FP32 MFMA.  Backward contractions are
+   FP32 in both modes.  Errors: FE_EINVAL (NULL, other dtype), FE_ENOMEM. */
+fe_status fe_gnn_create(uint64_t seed, fe_dtype compute, fe_gnn **out);
 void fe_gnn_free(fe_gnn *g);
 
 /* Host copies of the FP32 parameters in the flattened order.  set also

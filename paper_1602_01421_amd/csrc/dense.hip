@@ -471,6 +471,34 @@ __global__ void random_kernel(T* __restrict__ W, int64_t n, int32_t b, uint32_t 
   W[e] = to_storage<T, double>(v);
 }
 
+template <typename S, typename D>
+__global__ void convert_kernel(D* __restrict__ dst, const S* __restrict__ src, int64_t count) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) dst[e] = to_storage<D, double>(load_f64(src + e));
+}
+
+template <typename S>
+fe_status convert_from(void* dst, fe_dtype ddt, const S* src, int64_t count, hipStream_t s) {
+  const int64_t g = (count + 255) / 256;
+  if (g > 0x7FFFFFFF) return fail(FE_EUNSUPPORTED, "convert: too large");
+  switch (ddt) {
+    case FE_F64:
+      hipLaunchKernelGGL((convert_kernel<S, double>), dim3((uint32_t)g), dim3(256), 0, s,
+                         static_cast<double*>(dst), src, count);
+      break;
+    case FE_F32:
+      hipLaunchKernelGGL((convert_kernel<S, float>), dim3((uint32_t)g), dim3(256), 0, s,
+                         static_cast<float*>(dst), src, count);
+      break;
+    case FE_BF16:
+      hipLaunchKernelGGL((convert_kernel<S, bf16_t>), dim3((uint32_t)g), dim3(256), 0, s,
+                         static_cast<bf16_t*>(dst), src, count);
+      break;
+  }
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- launchers
@@ -593,4 +621,16 @@ fe_status random_fill(void* W, int64_t n, int32_t b, uint32_t mask, int32_t mode
   return FE_OK;
 }
 
+}  // namespace fe
+
+namespace fe {
+fe_status convert_launch(void* dst, fe_dtype ddt, const void* src, fe_dtype sdt, int64_t count,
+                         hipStream_t s) {
+  switch (sdt) {
+    case FE_F64: return convert_from(dst, ddt, static_cast<const double*>(src), count, s);
+    case FE_F32: return convert_from(dst, ddt, static_cast<const float*>(src), count, s);
+    case FE_BF16: return convert_from(dst, ddt, static_cast<const bf16_t*>(src), count, s);
+  }
+  return fail(FE_EINVAL, "convert: bad dtype");
+}
 }  // namespace fe

@@ -111,6 +111,10 @@ fe_status random_fill(void* W, int64_t n, int32_t b, uint32_t col_mask, int32_t 
                       uint64_t seed, uint32_t step, const int32_t* perm, fe_dtype dt,
                       hipStream_t s);
 
+// dst (count elements of ddt) <- src (sdt), rounded to nearest even
+fe_status convert_launch(void* dst, fe_dtype ddt, const void* src, fe_dtype sdt, int64_t count,
+                         hipStream_t s);
+
 bool sym_eig(int n, double* a, double* w, double* z);
 
 }  // namespace fe

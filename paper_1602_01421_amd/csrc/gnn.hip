@@ -195,6 +195,69 @@ __global__ __launch_bounds__(256) void layer_fwd_kernel(const float* __restrict_
   }
 }
 
+// Forward layer in FP32 (FP32 MFMA 16x16x4), for the FP32 compute mode.  The
+// contraction index k = (K / 4) * kk + ks is mapped so that lane (i, kk)
+// reads K / 4 contiguous inputs of its row (each range lies in one source).
+template <int DIN>
+__global__ __launch_bounds__(256) void layer_fwd_f32_kernel(const float* __restrict__ T,
+                                                            const float* __restrict__ Hp,
+                                                            const float* __restrict__ dinv,
+                                                            const float* __restrict__ W,
+                                                            const float* __restrict__ U,
+                                                            const float* __restrict__ bias,
+                                                            int64_t n, float* __restrict__ H,
+                                                            float* __restrict__ Hs) {
+  constexpr int K = 2 * DIN, KQ = K / 4, KS = K + 1;
+  __shared__ float Bs[HID * KS];
+  __shared__ float bs[HID];
+  for (int e = threadIdx.x; e < K * HID; e += blockDim.x) {
+    const int k = e / HID, j = e % HID;
+    Bs[j * KS + k] = k < DIN ? W[k * HID + j] : U[(k - DIN) * HID + j];
+  }
+  for (int j = threadIdx.x; j < HID; j += blockDim.x) bs[j] = bias[j];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, kk = lane >> 4;
+  const int k0 = KQ * kk;
+  for (int64_t tile = blockIdx.x; tile * 64 < n; tile += gridDim.x) {
+    const int64_t r0 = tile * 64 + wave * 16;
+    const int64_t row = r0 + i;
+    const int64_t rc = row < n ? row : n - 1;
+    const float sc = (row < n) ? (k0 < DIN ? dinv[rc] : 1.0f) : 0.0f;
+    const float* src = k0 < DIN ? T + rc * DIN + k0 : Hp + rc * DIN + (k0 - DIN);
+    float x[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; q += 4) {
+      const float4 p = *reinterpret_cast<const float4*>(src + q);
+      x[q] = p.x * sc;
+      x[q + 1] = p.y * sc;
+      x[q + 2] = p.z * sc;
+      x[q + 3] = p.w * sc;
+    }
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KQ; ++ks)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[ks], Bs[(16 * t + i) * KS + k0 + ks],
+                                                      acc[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t orow = r0 + 4 * kk + r;
+        const int col = 16 * t + i;
+        if (orow < n) {
+          const float h = fmaxf(acc[t][r] + bs[col], 0.0f);
+          H[orow * HID + col] = h;
+          Hs[orow * HID + col] = dinv[orow] * h;
+        }
+      }
+  }
+}
+
 // Backward through a layer's inputs: with dZ = dH * (H > 0),
 //   G1 = dinv * (dZ W^T)   (the input of the aggregation transpose)
 //   dHp = dZ U^T
@@ -397,6 +460,7 @@ int wgrad_sets(int64_t n) {
 // ------------------------------------------------------------------ host
 struct Gnn {
   int device = 0;
+  bool f32 = false;  // forward transforms on FP32 MFMA instead of BF16
   float* params = nullptr;  // FP32 masters
   float* grads = nullptr;
   float* m = nullptr;
@@ -455,14 +519,16 @@ fe_status forward(const Gnn& g, const Csr& A, const float* z, Ws& ws, Fwd& f, fl
   for (int l = 0; l < NLAYER; ++l) {
     const int din = l == 0 ? IN0 : HID;
     FE_TRY(spmm_launch(A, f.Hs[l], f.T[l], din, FE_F32, s));  // T = A (dinv * H)
-    if (l == 0)
-      hipLaunchKernelGGL((layer_fwd_kernel<IN0>), dim3(tiles), dim3(256), 0, s, f.T[0], f.H[0],
-                         f.dinv, g.params + o.W[0], g.params + o.U[0], g.params + o.b[0], n,
-                         f.H[1], f.Hs[1]);
-    else
-      hipLaunchKernelGGL((layer_fwd_kernel<HID>), dim3(tiles), dim3(256), 0, s, f.T[l], f.H[l],
-                         f.dinv, g.params + o.W[l], g.params + o.U[l], g.params + o.b[l], n,
-                         f.H[l + 1], f.Hs[l + 1]);
+#define FE_FWD(KERNEL, D)                                                                  \
+  hipLaunchKernelGGL((KERNEL<D>), dim3(tiles), dim3(256), 0, s, f.T[l], f.H[l], f.dinv,     \
+                     g.params + o.W[l], g.params + o.U[l], g.params + o.b[l], n, f.H[l + 1], \
+                     f.Hs[l + 1]);
+    if (l == 0) {
+      if (g.f32) FE_FWD(layer_fwd_f32_kernel, IN0) else FE_FWD(layer_fwd_kernel, IN0)
+    } else {
+      if (g.f32) FE_FWD(layer_fwd_f32_kernel, HID) else FE_FWD(layer_fwd_kernel, HID)
+    }
+#undef FE_FWD
     FE_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(out_fwd_kernel, grid1(n), dim3(256), 0, s, f.H[NLAYER], g.params + o.P, n,
@@ -482,8 +548,10 @@ extern "C" {
 
 int64_t fe_gnn_param_count(void) { return offsets().total; }
 
-fe_status fe_gnn_create(uint64_t seed, fe_gnn** out) {
+fe_status fe_gnn_create(uint64_t seed, fe_dtype compute, fe_gnn** out) {
   if (!out) return fail(FE_EINVAL, "fe_gnn_create: out is NULL");
+  if (compute != FE_BF16 && compute != FE_F32)
+    return fail(FE_EINVAL, "fe_gnn_create: compute must be FE_BF16 or FE_F32");
   const Offsets o = offsets();
   std::vector<float> h((size_t)o.total, 0.0f);
   // Glorot-uniform weights from Philox4x32-10 draws (counter: index, tensor id)
@@ -516,6 +584,7 @@ fe_status fe_gnn_create(uint64_t seed, fe_gnn** out) {
   }
   fill(o.P, HID, NOUT, 99);
   fe_gnn* g = new fe_gnn();
+  g->f32 = compute == FE_F32;
   if (hipGetDevice(&g->device) != hipSuccess) {
     delete g;
     return fail(FE_EDEVICE, "fe_gnn_create: no device");

@@ -94,6 +94,13 @@ struct DevBuf {
   ~DevBuf() {
     for (void* p : ptrs) hipFree(p);
   }
+  void release(void* p) {
+    for (auto& q : ptrs)
+      if (q == p) {
+        (void)hipFree(q);
+        q = nullptr;
+      }
+  }
   fe_status get(void** p, size_t bytes) {
     hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
     if (e != hipSuccess)
@@ -137,8 +144,11 @@ class Solver {
   double tol, eta;
   fe_ks_opts o;
   hipStream_t s;
-  fe_dtype dt;
+  fe_dtype dt, dt_final;
   size_t es;
+  bool mixed = false;
+  double mixed_switch = 1e-3;
+  int switch_restart = -1, spmm_low = 0;
   int64_t n, stride;
   char* V = nullptr;  // m/b + 1 blocks
   double *dC = nullptr, *dM = nullptr, *dY = nullptr, *dTheta = nullptr, *dSums = nullptr;
@@ -152,20 +162,62 @@ class Solver {
   int step = 0, refills = 0, spmm_calls = 0, spmm_cols = 0, gram_calls = 0, update_calls = 0;
   double t_host = 0.0;
   double bytes[4] = {0, 0, 0, 0};  // algorithmic HBM bytes per kernel class
+  std::vector<double> worst_hist;
 
   Solver(const Csr& A_, int nev_, int b_, int m_, double tol_, const fe_ks_opts& o_)
       : A(A_), nev(nev_), b(b_), m(m_), tol(tol_), o(o_) {
     s = (hipStream_t)o.hip_stream;
-    dt = o.dt;
+    dt_final = o.dt;
+    mixed = o.mixed != 0 && o.dt != FE_BF16;
+    if (o.mixed_switch > 0) mixed_switch = o.mixed_switch;
+    dt = mixed ? FE_BF16 : o.dt;
     es = dtype_size(dt);
     n = A.n;
     stride = n * b;
-    eta = o.eta > 0 ? o.eta : (dt == FE_F64 ? 1e-6 : dt == FE_F32 ? 1e-5 : 3e-2);
+    set_eta();
     prof.on = o.profile != 0;
     prof.s = s;
   }
 
+  void set_eta() { eta = o.eta > 0 ? o.eta : (dt == FE_F64 ? 1e-6 : dt == FE_F32 ? 1e-5 : 3e-2); }
+
   void* blk(int j) { return V + (size_t)j * stride * es; }
+
+  // Mixed precision switch.  Widening the BF16 basis in place would keep the
+  // Krylov relation A V = V T + Q B only to BF16 accuracy, and thick restarts
+  // never purge that error (the implicit residuals keep falling while the
+  // explicit ones stay near 2^-8).  Instead the solve restarts explicitly in
+  // dt_final from one block that sums the wanted Ritz vectors: column j holds
+  // sum_{i = j mod b, i < q} V y_i with q = nev rounded up to a multiple of b,
+  // so q/b block steps already span every wanted Ritz direction again.
+  fe_status widen_restart(const std::vector<double>& Y) {
+    const int nblk = m / b + 1;
+    const int q = std::min(m, (nev + b - 1) / b * b);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < b; ++j) {
+        double sum = 0.0;
+        for (int t = j; t < q; t += b) sum += Y[(size_t)i * m + t];
+        hY[(size_t)i * b + j] = sum;
+      }
+    FE_HIP(hipMemcpyAsync(dY, hY, sizeof(double) * m * b, hipMemcpyHostToDevice, s));
+    const size_t es2 = dtype_size(dt_final);
+    char* V2 = nullptr;
+    double* tmp = nullptr;
+    FE_TRY(dev.get((void**)&V2, (size_t)nblk * stride * es2));
+    FE_TRY(dev.get((void**)&tmp, (size_t)n * b * sizeof(double)));
+    prof.begin(P_OTHER);
+    FE_TRY(combine_launch(tmp, b, n, b, V, m / b, stride, dY, dt, s));
+    FE_TRY(convert_launch(V2, dt_final, tmp, FE_F64, (int64_t)n * b, s));
+    prof.end();
+    FE_TRY(sync());
+    dev.release(tmp);
+    dev.release(V);
+    V = V2;
+    dt = dt_final;
+    es = es2;
+    set_eta();
+    return FE_OK;
+  }
 
   fe_status setup() {
     const int nblk = m / b + 1;
@@ -380,7 +432,17 @@ class Solver {
     const int32_t* perm = A.relabeled ? A.d_perm : nullptr;
     // start block into block 0 (internal numbering)
     prof.begin(P_OTHER);
-    if (o.start) {
+    if (o.start && dt != dt_final) {  // mixed: bring the caller's block to the storage dtype
+      void* tmp = nullptr;
+      FE_TRY(dev.get(&tmp, (size_t)n * b * dtype_size(dt_final)));
+      if (perm)
+        FE_TRY(permute_rows(tmp, o.start, perm, n, b, dt_final, false, s));
+      else
+        FE_TRY(copy_block(tmp, o.start, n, b, dt_final, s));
+      FE_TRY(convert_launch(blk(0), dt, tmp, dt_final, n * b, s));
+      FE_TRY(sync());
+      dev.release(tmp);
+    } else if (o.start) {
       if (perm)
         FE_TRY(permute_rows(blk(0), o.start, perm, n, b, dt, false, s));
       else
@@ -403,6 +465,7 @@ class Solver {
         const int wb = k / b;
         FE_TRY(spmm(blk(wb - 1), blk(wb), b));
         ++spmm_calls;
+        if (dt != dt_final) ++spmm_low;
         ++step;
         FE_TRY(orth_block(wb, C, R));
         auto th = clk::now();
@@ -455,6 +518,23 @@ class Solver {
                 restarts, spmm_calls, nconv, nev, worst, theta[0]);
       }
       if (converged || restarts >= max_restarts) break;
+      if (dt != dt_final) {  // mixed: widen once BF16 stalls or is good enough
+        double worst = 0.0;
+        for (int j = 0; j < nev; ++j) worst = std::max(worst, rho[j]);
+        worst_hist.push_back(worst);
+        const size_t h = worst_hist.size();
+        const bool stalled = h >= 3 && worst > 0.5 * worst_hist[h - 3];
+        if (worst < mixed_switch || stalled) {
+          FE_TRY(widen_restart(Y));
+          switch_restart = restarts;
+          std::fill(T.begin(), T.end(), 0.0);
+          std::fill(Bk.begin(), Bk.end(), 0.0);
+          FE_TRY(orth_block(0, C, R));
+          k = 0;
+          ++restarts;
+          continue;
+        }
+      }
       // restart
       const int p = m - b * std::max(1, (m - nev) / (2 * b));
       for (int i = 0; i < m; ++i)
@@ -509,7 +589,7 @@ class Solver {
     FE_HIP(hipMemcpyAsync(dTheta, hTheta, sizeof(double) * nev, hipMemcpyHostToDevice, s));
     prof.begin(P_OTHER);
     FE_TRY(resid_launch(AX, X, n, nev, dTheta, dSums, dPartRes, s));
-    if (evecs) FE_TRY(store_rows(evecs, X, perm, n, nev, dt, s));
+    if (evecs) FE_TRY(store_rows(evecs, X, perm, n, nev, dt_final, s));  // caller's dtype
     prof.end();
     FE_HIP(hipMemcpyAsync(hSums, dSums, sizeof(double) * 3 * nev, hipMemcpyDeviceToHost, s));
     FE_TRY(sync());
@@ -523,6 +603,8 @@ class Solver {
       rep->refills = refills;
       rep->gram_calls = gram_calls;
       rep->update_calls = update_calls;
+      rep->switch_restart = switch_restart;
+      rep->spmm_calls_low = spmm_low;
       for (int j = 0; j < nev; ++j) {
         rep->rho[j] = rho[j];
         rep->ritz[j] = theta[j];

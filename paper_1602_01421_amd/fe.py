@@ -39,14 +39,16 @@ class KsOpts(ctypes.Structure):
                 ("max_restarts", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("start", ctypes.c_void_p), ("hip_stream", ctypes.c_void_p),
                 ("eta", ctypes.c_double), ("profile", ctypes.c_int32),
-                ("verbose", ctypes.c_int32)]
+                ("verbose", ctypes.c_int32), ("mixed", ctypes.c_int32),
+                ("mixed_switch", ctypes.c_double)]
 
 
 class KsReport(ctypes.Structure):
     _fields_ = [("restarts", ctypes.c_int32), ("spmm_calls", ctypes.c_int32),
                 ("spmm_cols", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("refills", ctypes.c_int32), ("gram_calls", ctypes.c_int32),
-                ("update_calls", ctypes.c_int32),
+                ("update_calls", ctypes.c_int32), ("switch_restart", ctypes.c_int32),
+                ("spmm_calls_low", ctypes.c_int32),
                 ("rho", ctypes.c_double * 64), ("ritz", ctypes.c_double * 64),
                 ("resid", ctypes.c_double * 64),
                 ("t_spmm", ctypes.c_double), ("t_gram", ctypes.c_double),
@@ -82,7 +84,7 @@ def lib():
             "fe_krylov_schur": [P, i32, i32, i32, f64, ctypes.POINTER(KsOpts), P, P,
                                 ctypes.POINTER(KsReport)],
             "fe_dense_symeig": [i32, P, P, P],
-            "fe_gnn_create": [ctypes.c_uint64, ctypes.POINTER(P)],
+            "fe_gnn_create": [ctypes.c_uint64, i32, ctypes.POINTER(P)],
             "fe_gnn_get_params": [P, P],
             "fe_gnn_set_params": [P, P],
             "fe_gnn_forward": [P, P, P, P, P],
@@ -253,6 +255,8 @@ class KsResult:
     refills: int
     gram_calls: int
     update_calls: int
+    switch_restart: int
+    spmm_calls_low: int
     rho: np.ndarray
     ritz: np.ndarray
     resid: np.ndarray
@@ -270,7 +274,8 @@ class KsResult:
 def fe_krylov_schur(A: Csr, nev: int, block: int, m: int, tol: float, dtype=None, start=None,
                     seed: int = 0, max_restarts: int = 0, eta: float = 0.0, stream=None,
                     want_vectors: bool = True, profile: bool = False,
-                    verbose: bool = False) -> KsResult:
+                    verbose: bool = False, mixed: bool = False,
+                    mixed_switch: float = 0.0) -> KsResult:
     """Block Krylov-Schur for the nev largest-magnitude eigenpairs (see fe.h)."""
     import torch
     if dtype is None:
@@ -284,6 +289,8 @@ def fe_krylov_schur(A: Csr, nev: int, block: int, m: int, tol: float, dtype=None
     o.eta = eta
     o.profile = int(profile)
     o.verbose = int(verbose)
+    o.mixed = int(mixed)
+    o.mixed_switch = mixed_switch
     o.hip_stream = _stream(stream).value
     if start is not None:
         if start.shape != (A.n, block) or start.dtype != dtype:
@@ -298,7 +305,8 @@ def fe_krylov_schur(A: Csr, nev: int, block: int, m: int, tol: float, dtype=None
     return KsResult(evals=evals, evecs=evecs, status=st, restarts=rep.restarts,
                     spmm_calls=rep.spmm_calls, spmm_cols=rep.spmm_cols,
                     converged=rep.converged, refills=rep.refills, gram_calls=rep.gram_calls,
-                    update_calls=rep.update_calls, rho=np.array(rep.rho[:nev]),
+                    update_calls=rep.update_calls, switch_restart=rep.switch_restart,
+                    spmm_calls_low=rep.spmm_calls_low, rho=np.array(rep.rho[:nev]),
                     ritz=np.array(rep.ritz[:nev]),
                     resid=np.array(rep.resid[:nev]), t_spmm=rep.t_spmm, t_gram=rep.t_gram,
                     t_update=rep.t_update, t_other_dev=rep.t_other_dev,
@@ -340,9 +348,10 @@ def gnn_flatten(params: dict) -> np.ndarray:
 class Gnn:
     """Owning wrapper of an fe_gnn (learned start-block network)."""
 
-    def __init__(self, seed: int = 0):
+    def __init__(self, seed: int = 0, compute: str = "bf16"):
         h = ctypes.c_void_p()
-        _check(lib().fe_gnn_create(seed, ctypes.byref(h)))
+        dt = {"bf16": FE_BF16, "f32": FE_F32}[compute]
+        _check(lib().fe_gnn_create(seed, dt, ctypes.byref(h)))
         self._h = h
         self.count = int(lib().fe_gnn_param_count())
 

@@ -129,3 +129,41 @@ def test_no_convergence_and_bad_args(fe):
         with pytest.raises(fe.FeError) as e:
             fe.fe_krylov_schur(A, *args, 1e-8)
         assert e.value.status in (fe.FE_EINVAL, fe.FE_EUNSUPPORTED)
+
+
+def test_mixed_precision_bf16_to_fp32(fe):
+    """Storage starts in BF16 and is widened to FP32 in place of the Krylov
+    state; the solve still reaches tol 1e-6 and the FP64-oracle eigenvalues."""
+    g = S.rmat_edges(14, seed=14)
+    A, rp, ci = setup(fe, g)
+    ref = oracle_ks(rp, ci, A.n, 8, 8, 64, 1e-12, S.normal((A.n, 8), seed=3))
+    r = fe.fe_krylov_schur(A, 8, 8, 64, 1e-6, dtype=torch.float32, seed=3, mixed=True)
+    assert r.status == fe.FE_OK
+    assert r.switch_restart >= 0 and 0 < r.spmm_calls_low < r.spmm_calls
+    assert np.all(np.abs(r.evals - ref.evals) <= 1e-8 * np.abs(ref.evals))
+    assert r.resid.max() <= 1e-6
+    assert r.evecs.dtype == torch.float32
+    check_vectors(rp, ci, r)
+
+
+def test_rmat22_full_size_fp32(fe):
+    """R-MAT scale 22 (the benchmark graph), FP32 storage, nev 8, block 4,
+    m 48, tol 1e-6, against an FP64-storage solve of the same graph; the FP32
+    eigenvectors are certified by the oracle's FP64 product: every returned
+    value lies within its explicit residual of an eigenvalue of A, and
+    matches the FP64 solve to 1e-8 relative."""
+    n, s, d = S.rmat_edges(22, seed=22)
+    A = fe.fe_csr_build(n, s, d, fe.FE_GRAPH_DEFAULT | fe.FE_RELABEL_BY_DEGREE)
+    r32 = fe.fe_krylov_schur(A, 8, 4, 48, 1e-6, dtype=torch.float32, seed=1)
+    r64 = fe.fe_krylov_schur(A, 8, 4, 48, 1e-10, dtype=torch.float64, seed=2, want_vectors=False)
+    assert r32.status == fe.FE_OK and r64.status == fe.FE_OK
+    assert np.all(np.abs(r32.evals - r64.evals) <= 1e-8 * np.abs(r64.evals))
+    assert r32.resid.max() <= 1e-6
+    rp, ci = O.csr_from_edges(n, s, d)
+    X = r32.evecs.double().cpu().numpy()
+    R = O.spmm(rp, ci, X, threads=16) - X * r32.evals
+    res = np.linalg.norm(R, axis=0) / np.linalg.norm(X, axis=0)
+    # the returned vectors are the FP64 Ritz vectors rounded to FP32, which adds
+    # up to about 2^-24 * ||A|| (||A|| = |lambda_1|) to each residual
+    rounding = 2.0 ** -23 * np.abs(r64.evals).max()
+    assert np.all(res <= 1e-6 * np.abs(r32.evals) + rounding)
