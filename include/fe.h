@@ -158,10 +158,13 @@ typedef struct {
   double eta;            /* dependence threshold; 0 -> 1e-6 (F64), 1e-5 (F32), 3e-2 (BF16) */
   int32_t profile;       /* 1 = time each kernel class with HIP events */
   int32_t verbose;       /* 1 = print one line per restart to stderr */
-  int32_t mixed;         /* 1 = mixed-precision storage: the subspace starts in BF16
-                            and is widened to dt (FP32 or FP64) once the BF16
-                            iteration stalls or its worst residual estimate drops
-                            below mixed_switch; the Krylov state carries over */
+  int32_t mixed;         /* 1 = mixed-precision storage: the subspace starts in BF16;
+                            once the worst wanted residual estimate drops below
+                            mixed_switch, or gains less than 10% on the best of the
+                            three restarts before (stall), the solve restarts in dt
+                            (FP32 or FP64) from one block that sums the wanted Ritz
+                            vectors (column j: those with index = j mod block).
+                            The caller's start block, if any, is rounded to BF16. */
   double mixed_switch;   /* 0 -> 1e-3 */
 } fe_ks_opts;
 
@@ -225,6 +228,13 @@ fe_status fe_krylov_schur(const fe_csr *A, int32_t nev, int32_t block, int32_t m
  * (the library permutes for relabelled handles).  Loss against eigenvectors
  * V (n x 8, orthonormal): L = 1 - ||V^T Q||_F^2 / 8 with Q an orthonormal
  * basis of span(X).
+ *
+ * Memory: each handle owns a device workspace sized to the largest call it
+ * has served (inference: 4 x n x 64 + 9n floats; training keeps every
+ * activation), held until fe_gnn_free; a call that needs more than the
+ * current workspace takes stream-ordered allocations once and the next call
+ * grows the workspace.  Calls on one handle must not overlap (they share the
+ * workspace, the gradients and the Adam state).
  * ---------------------------------------------------------------------- */
 typedef struct fe_gnn fe_gnn;
 
@@ -255,8 +265,11 @@ fe_status fe_gnn_backward(fe_gnn *g, const fe_csr *A, const float *z, const floa
                           double *loss, float *grads_host, void *hip_stream);
 
 /* One Adam step (Kingma & Ba: beta1 0.9, beta2 0.999, eps 1e-8, bias
-   corrected) with the gradients stored by the last fe_gnn_backward. */
-fe_status fe_gnn_adam(fe_gnn *g, double lr, void *hip_stream);
+   corrected) with the gradients stored by the last fe_gnn_backward.  clip > 0
+   first scales the gradients by min(1, clip / ||g||_2), the norm taken over
+   all parameters (global-norm clipping); clip == 0 disables it.  Asynchronous
+   on the stream.  Errors: FE_EINVAL (NULL, no stored gradients, clip < 0). */
+fe_status fe_gnn_adam(fe_gnn *g, double lr, double clip, void *hip_stream);
 
 /*
  * Host utility: eigendecomposition of a small dense symmetric matrix (the

@@ -118,10 +118,19 @@ def init_params(seed: int = 0, scale: float = 1.0):
     return p
 
 
-def adam_step(params, grads, state, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
-    """One Adam update (Kingma & Ba 2015) with bias correction."""
+def adam_step(params, grads, state, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, clip=0.0):
+    """One Adam update (Kingma & Ba 2015) with bias correction.
+
+    clip > 0: the gradients are first scaled by min(1, clip / ||g||), ||g||
+    the 2-norm over all tensors together (global-norm clipping, Pascanu et
+    al. 2013).
+    """
     t = state.get("t", 0) + 1
     state["t"] = t
+    if clip > 0:
+        norm = np.sqrt(sum(float(np.sum(np.square(g))) for g in grads.values()))
+        scale = min(1.0, clip / norm) if norm > 0 else 1.0
+        grads = {k: g * scale for k, g in grads.items()}
     for k in params:
         m = state.setdefault("m_" + k, np.zeros_like(params[k]))
         v = state.setdefault("v_" + k, np.zeros_like(params[k]))

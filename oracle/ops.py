@@ -65,12 +65,14 @@ def spmm_rows_from_edges(n: int, src: np.ndarray, dst: np.ndarray, X: np.ndarray
     deduplicated, loop-free pattern of the edge stream, without building A.
     Each row sums its neighbours' X rows in ascending neighbour order."""
     rows = np.asarray(rows, dtype=np.int64)
-    s = np.asarray(src, dtype=np.int64)
-    d = np.asarray(dst, dtype=np.int64)
-    m1 = np.isin(s, rows)
-    m2 = np.isin(d, rows)
-    u = np.concatenate([s[m1], d[m2]])
-    v = np.concatenate([d[m1], s[m2]])
+    s = np.asarray(src)
+    d = np.asarray(dst)
+    mark = np.zeros(n, dtype=bool)
+    mark[rows] = True
+    m1 = mark[s]
+    m2 = mark[d]
+    u = np.concatenate([s[m1], d[m2]]).astype(np.int64)
+    v = np.concatenate([d[m1], s[m2]]).astype(np.int64)
     keep = u != v
     key = np.unique(u[keep] * np.int64(n) + v[keep])
     ru = key // n

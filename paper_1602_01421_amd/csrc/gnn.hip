@@ -438,12 +438,31 @@ __global__ void place_grads_kernel(const float* __restrict__ C, int din, float* 
   else gb[c] = C[e];
 }
 
+// scale = min(1, clip / ||g||_2) over all parameters; one workgroup, fixed
+// summation order (strided FP64 partial sums, then a tree in LDS).
+__global__ __launch_bounds__(1024) void clip_scale_kernel(const float* __restrict__ g, int count,
+                                                          float clip, float* __restrict__ scale) {
+  __shared__ double red[1024];
+  double sum = 0.0;
+  for (int e = threadIdx.x; e < count; e += 1024) sum += (double)g[e] * (double)g[e];
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 512; off >= 1; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double norm = sqrt(red[0]);
+    scale[0] = norm > clip ? (float)(clip / norm) : 1.0f;
+  }
+}
+
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
                             float* __restrict__ m, float* __restrict__ v, int count, float lr,
-                            float c1, float c2) {
+                            float c1, float c2, const float* __restrict__ scale) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= count) return;
-  const float gi = g[e];
+  const float gi = scale ? g[e] * scale[0] : g[e];
   const float mi = 0.9f * m[e] + 0.1f * gi;
   const float vi = 0.999f * v[e] + 0.001f * gi * gi;
   m[e] = mi;
@@ -465,22 +484,56 @@ struct Gnn {
   float* grads = nullptr;
   float* m = nullptr;
   float* v = nullptr;
+  float* gscale = nullptr;  // gradient clipping factor (device scalar)
   int step = 0;
   bool have_grads = false;
+  // Workspace arena: grown (at the start of a call) to the largest total a
+  // previous call needed, so steady-state calls allocate nothing.
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_need = 0;
 };
 
 namespace {
 
-struct Ws {  // stream-ordered workspace of one call
+// Workspace of one call: bump allocation from the handle's arena; a request
+// that does not fit (first calls, or a larger graph) falls back to a
+// stream-ordered allocation and raises the arena's target size, which the
+// next call allocates before it starts.
+struct Ws {
   hipStream_t s;
+  Gnn* g;
+  size_t off = 0, need = 0;
   std::vector<void*> ptrs;
-  explicit Ws(hipStream_t st) : s(st) {}
+  Ws(hipStream_t st, Gnn* gn) : s(st), g(gn) {}
+  fe_status grow() {
+    if (g->arena_need <= g->arena_cap) return FE_OK;
+    if (g->arena) {
+      FE_HIP(hipStreamSynchronize(s));
+      FE_HIP(hipFree(g->arena));
+      g->arena = nullptr;
+      g->arena_cap = 0;
+    }
+    if (hipMalloc((void**)&g->arena, g->arena_need) != hipSuccess) {
+      g->arena = nullptr;
+      return fail(FE_ENOMEM, "gnn workspace: %zu bytes", g->arena_need);
+    }
+    g->arena_cap = g->arena_need;
+    return FE_OK;
+  }
   ~Ws() {
     for (void* p : ptrs) (void)hipFreeAsync(p, s);
+    g->arena_need = std::max(g->arena_need, need);
   }
   template <class T>
   fe_status get(T** p, size_t count) {
-    hipError_t e = hipMallocAsync((void**)p, std::max<size_t>(count, 64) * sizeof(T), s);
+    const size_t bytes = (std::max<size_t>(count, 64) * sizeof(T) + 255) & ~(size_t)255;
+    need += bytes;
+    if (off + bytes <= g->arena_cap) {
+      *p = reinterpret_cast<T*>(g->arena + off);
+      off += bytes;
+      return FE_OK;
+    }
+    hipError_t e = hipMallocAsync((void**)p, bytes, s);
     if (e != hipSuccess) return fail(FE_ENOMEM, "gnn workspace: %s", hipGetErrorString(e));
     ptrs.push_back(*p);
     return FE_OK;
@@ -495,22 +548,40 @@ struct Fwd {
   float *dinv, *H[4], *Hs[4], *T[3], *X, *Xorig;
 };
 
-// Forward pass; keeps the activations needed by the backward pass.
-fe_status forward(const Gnn& g, const Csr& A, const float* z, Ws& ws, Fwd& f, float* Xorig) {
+// Forward pass.  With keep, every activation stays for the backward pass;
+// without it (inference) four n x 64 buffers are reused across layers: layer l
+// reads H[l] and T[l] and writes H[l+1] and Hs[l+1], so H alternates between
+// two buffers, while Hs and T each need one (Hs[l] is consumed by the product
+// that makes T[l] before layer l writes Hs[l+1]; T[l] is read only by layer l).
+fe_status forward(const Gnn& g, const Csr& A, const float* z, Ws& ws, Fwd& f, float* Xorig,
+                  bool keep = true) {
   const int64_t n = A.n;
   const Offsets o = offsets();
   hipStream_t s = ws.s;
   const int32_t* perm = A.relabeled ? A.d_perm : nullptr;
   FE_TRY(ws.get(&f.dinv, n));
-  FE_TRY(ws.get(&f.H[0], n * IN0));
-  FE_TRY(ws.get(&f.Hs[0], n * IN0));
-  for (int l = 1; l <= NLAYER; ++l) {
-    FE_TRY(ws.get(&f.H[l], n * HID));
-    FE_TRY(ws.get(&f.Hs[l], n * HID));
+  if (keep) {
+    FE_TRY(ws.get(&f.H[0], n * IN0));
+    FE_TRY(ws.get(&f.Hs[0], n * IN0));
+    for (int l = 1; l <= NLAYER; ++l) {
+      FE_TRY(ws.get(&f.H[l], n * HID));
+      FE_TRY(ws.get(&f.Hs[l], n * HID));
+    }
+    FE_TRY(ws.get(&f.T[0], n * IN0));
+    FE_TRY(ws.get(&f.T[1], n * HID));
+    FE_TRY(ws.get(&f.T[2], n * HID));
+  } else {
+    float *ha, *hb, *hs, *t;
+    FE_TRY(ws.get(&ha, n * HID));
+    FE_TRY(ws.get(&hb, n * HID));
+    FE_TRY(ws.get(&hs, n * HID));
+    FE_TRY(ws.get(&t, n * HID));
+    for (int l = 0; l <= NLAYER; ++l) {
+      f.H[l] = (l % 2) ? hb : ha;
+      f.Hs[l] = hs;
+    }
+    for (int l = 0; l < NLAYER; ++l) f.T[l] = t;
   }
-  FE_TRY(ws.get(&f.T[0], n * IN0));
-  FE_TRY(ws.get(&f.T[1], n * HID));
-  FE_TRY(ws.get(&f.T[2], n * HID));
   FE_TRY(ws.get(&f.X, n * NOUT));
   hipLaunchKernelGGL(features_kernel, grid1(n), dim3(256), 0, s, A.d_row_ptr, z, perm, n, f.H[0],
                      f.Hs[0], f.dinv);
@@ -592,7 +663,8 @@ fe_status fe_gnn_create(uint64_t seed, fe_dtype compute, fe_gnn** out) {
   const size_t bytes = sizeof(float) * o.total;
   if (hipMalloc((void**)&g->params, bytes) != hipSuccess ||
       hipMalloc((void**)&g->grads, bytes) != hipSuccess ||
-      hipMalloc((void**)&g->m, bytes) != hipSuccess || hipMalloc((void**)&g->v, bytes) != hipSuccess) {
+      hipMalloc((void**)&g->m, bytes) != hipSuccess || hipMalloc((void**)&g->v, bytes) != hipSuccess ||
+      hipMalloc((void**)&g->gscale, sizeof(float)) != hipSuccess) {
     fe_gnn_free(g);
     return fail(FE_ENOMEM, "fe_gnn_create: hipMalloc failed");
   }
@@ -610,6 +682,8 @@ void fe_gnn_free(fe_gnn* g) {
   if (!g) return;
   (void)hipFree(g->params);
   (void)hipFree(g->grads);
+  (void)hipFree(g->gscale);
+  (void)hipFree(g->arena);
   (void)hipFree(g->m);
   (void)hipFree(g->v);
   delete g;
@@ -637,9 +711,10 @@ fe_status fe_gnn_forward(fe_gnn* g, const fe_csr* A, const float* z, float* X, v
   if (!g || !A || !z || !X) return fail(FE_EINVAL, "fe_gnn_forward: NULL argument");
   hipStream_t s = (hipStream_t)stream;
   {
-    Ws ws(s);
+    Ws ws(s, g);
+    FE_TRY(ws.grow());
     Fwd f;
-    FE_TRY(forward(*g, *A, z, ws, f, X));
+    FE_TRY(forward(*g, *A, z, ws, f, X, false));
   }
   FE_HIP(hipStreamSynchronize(s));
   return FE_OK;
@@ -654,7 +729,8 @@ fe_status fe_gnn_backward(fe_gnn* g, const fe_csr* A, const float* z, const floa
   const Offsets o = offsets();
   const int32_t* perm = A->relabeled ? A->d_perm : nullptr;
   {
-    Ws ws(s);
+    Ws ws(s, g);
+    FE_TRY(ws.grow());
     Fwd f;
     FE_TRY(forward(*g, *A, z, ws, f, nullptr));
     // targets in the internal order
@@ -778,16 +854,22 @@ fe_status fe_gnn_backward(fe_gnn* g, const fe_csr* A, const float* z, const floa
   return FE_OK;
 }
 
-fe_status fe_gnn_adam(fe_gnn* g, double lr, void* stream) {
+fe_status fe_gnn_adam(fe_gnn* g, double lr, double clip, void* stream) {
   if (!g) return fail(FE_EINVAL, "fe_gnn_adam: NULL");
+  if (!(clip >= 0.0)) return fail(FE_EINVAL, "fe_gnn_adam: clip must be >= 0");
   if (!g->have_grads) return fail(FE_EINVAL, "fe_gnn_adam: no gradients (call fe_gnn_backward)");
   hipStream_t s = (hipStream_t)stream;
   g->step += 1;
   const float c1 = (float)(1.0 - std::pow(0.9, g->step));
   const float c2 = (float)(1.0 - std::pow(0.999, g->step));
   const int count = offsets().total;
+  if (clip > 0.0) {
+    hipLaunchKernelGGL(clip_scale_kernel, dim3(1), dim3(1024), 0, s, g->grads, count, (float)clip,
+                       g->gscale);
+    FE_HIP(hipGetLastError());
+  }
   hipLaunchKernelGGL(adam_kernel, grid1(count), dim3(256), 0, s, g->params, g->grads, g->m, g->v,
-                     count, (float)lr, c1, c2);
+                     count, (float)lr, c1, c2, clip > 0.0 ? g->gscale : nullptr);
   FE_HIP(hipGetLastError());
   return FE_OK;
 }

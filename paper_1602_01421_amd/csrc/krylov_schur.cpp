@@ -523,7 +523,9 @@ class Solver {
         for (int j = 0; j < nev; ++j) worst = std::max(worst, rho[j]);
         worst_hist.push_back(worst);
         const size_t h = worst_hist.size();
-        const bool stalled = h >= 3 && worst > 0.5 * worst_hist[h - 3];
+        // stalled: no 10% gain over the best of the three restarts before
+        const bool stalled =
+            h >= 4 && worst > 0.9 * std::min({worst_hist[h - 2], worst_hist[h - 3], worst_hist[h - 4]});
         if (worst < mixed_switch || stalled) {
           FE_TRY(widen_restart(Y));
           switch_restart = restarts;

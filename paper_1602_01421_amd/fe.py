@@ -89,7 +89,7 @@ def lib():
             "fe_gnn_set_params": [P, P],
             "fe_gnn_forward": [P, P, P, P, P],
             "fe_gnn_backward": [P, P, P, P, ctypes.POINTER(ctypes.c_double), P, P],
-            "fe_gnn_adam": [P, f64, P],
+            "fe_gnn_adam": [P, f64, f64, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -382,8 +382,9 @@ class Gnn:
                                      _stream(stream)))
         return loss.value, g
 
-    def adam(self, lr: float = 1e-3, stream=None):
-        _check(lib().fe_gnn_adam(self._h, lr, _stream(stream)))
+    def adam(self, lr: float = 1e-3, clip: float = 0.0, stream=None):
+        """One Adam step; clip > 0 scales the gradients to global norm <= clip first."""
+        _check(lib().fe_gnn_adam(self._h, lr, clip, _stream(stream)))
 
     def close(self):
         if self._h:

@@ -54,16 +54,21 @@ def label(A, seed: int = 1):
 
 
 def learned_start(net, A, z, dtype):
-    """Start block from the network, or None when it must fall back to random."""
-    torch = _torch()
+    """Start block from the network, or None when it must fall back to random.
+
+    One FP64 Gram of the output decides: a non-finite entry, or a smallest
+    eigenvalue below 1e-10 of the largest (numerically dependent columns),
+    means fallback.
+    """
+    from . import fe as F
     X = net.forward(A, z)
-    if not torch.isfinite(X).all():
+    G = F.fe_gram(X.unsqueeze(0), X).cpu().numpy()
+    if not np.all(np.isfinite(G)):
         return None
-    G = (X.double().T @ X.double()).cpu().numpy()
-    w = np.linalg.eigvalsh(G)
+    w = np.linalg.eigvalsh(0.5 * (G + G.T))
     if not (w[0] > 1e-10 * w[-1]):
         return None
-    return X.to(dtype).contiguous()
+    return X if X.dtype == dtype else X.to(dtype).contiguous()
 
 
 def solve(A, start=None, seed=0, dtype=None, tol=1e-8):
@@ -74,38 +79,76 @@ def solve(A, start=None, seed=0, dtype=None, tol=1e-8):
                              want_vectors=False)
 
 
-def train(args):
+def _labelled(args, first_seed, count, t0, tag, budget):
     from . import fe as F
-    torch = _torch()
-    net = F.Gnn(seed=args.init_seed)
     data = []
-    t0 = time.time()
-    for gi in range(args.graphs):
-        seed = args.first_seed + gi
+    for gi in range(count):
+        seed = first_seed + gi
         A, z, desc = build_graph(seed, args.max_log2n)
         V, r = label(A)
+        if r.status != F.FE_OK:
+            print(f"[train] skipped {tag} {desc}: label solve status {r.status}", flush=True)
+            continue
         data.append((A, z, V))
         if gi % 50 == 0:
-            print(f"[train] labelled {gi + 1}/{args.graphs}: {desc} products {r.spmm_calls} "
+            print(f"[train] labelled {tag} {gi + 1}/{count}: {desc} products {r.spmm_calls} "
                   f"({time.time() - t0:.0f} s)", flush=True)
-    history = []
+        if time.time() - t0 > budget:
+            print(f"[train] label budget reached after {len(data)} {tag} graphs", flush=True)
+            break
+    return data
+
+
+def train(args):
+    """Label the training and validation graphs, then run Adam epochs.
+
+    Step size: cosine decay from lr to lr/20 over the planned steps; the
+    gradients are clipped to global norm `clip`.  After every epoch the mean
+    loss over the validation graphs is taken, and the weights with the lowest
+    validation loss so far are written to args.out.  Labelling stops at
+    label_budget seconds and the epochs at time_budget seconds (whole run).
+    """
+    from . import fe as F
+    torch = _torch()
+    net = F.Gnn(seed=args.init_seed, compute=args.compute)
+    t0 = time.time()
+    val = _labelled(args, args.val_seed, args.val, t0, "validation", args.label_budget)
+    data = _labelled(args, args.first_seed, args.graphs, t0, "training", args.label_budget)
+    t_label = time.time() - t0
+    history, val_hist = [], []
     rng = np.random.default_rng(args.init_seed)
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    total_steps = max(1, args.epochs * len(data))
+    step = 0
+    best = float("inf")
     for ep in range(args.epochs):
+        t_ep = time.time()
         order = rng.permutation(len(data))
         losses = []
         for i in order:
             A, z, V = data[i]
+            lr = args.lr * (0.05 + 0.95 * 0.5 * (1.0 + np.cos(np.pi * step / total_steps)))
             loss, _ = net.backward(A, z, V)
-            net.adam(args.lr)
+            if np.isfinite(loss):
+                net.adam(lr, clip=args.clip)
             losses.append(loss)
-        history.append(float(np.mean(losses)))
+            step += 1
+        history.append(float(np.nanmean(losses)))
+        vl = float(np.mean([net.backward(A, z, V)[0] for A, z, V in val])) if val else history[-1]
+        val_hist.append(vl)
+        if vl < best:
+            best = vl
+            np.save(args.out, net.get_params())
         print(f"[train] epoch {ep + 1}/{args.epochs}: mean loss {history[-1]:.4f} "
-              f"({time.time() - t0:.0f} s)", flush=True)
+              f"validation {vl:.4f} (best {best:.4f}) ({time.time() - t0:.0f} s)", flush=True)
+        if time.time() - t0 + (time.time() - t_ep) > args.time_budget:
+            print("[train] time budget reached", flush=True)
+            break
     torch.cuda.synchronize()
-    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
-    np.save(args.out, net.get_params())
-    print(json.dumps({"train_loss": history, "graphs": args.graphs, "epochs": args.epochs,
-                      "seconds": time.time() - t0}), flush=True)
+    print(json.dumps({"train_loss": history, "val_loss": val_hist, "best_val_loss": best,
+                      "graphs": len(data), "val_graphs": len(val), "epochs": len(history),
+                      "label_s": t_label, "seconds": time.time() - t0, "lr": args.lr,
+                      "clip": args.clip, "compute": args.compute}), flush=True)
 
 
 def evaluate(weights, heldout, first_seed=3000, max_log2n=18, random_seeds=3, log=print):
@@ -128,23 +171,41 @@ def evaluate(weights, heldout, first_seed=3000, max_log2n=18, random_seeds=3, lo
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         X = learned_start(net, A, z, torch.float64)
+        torch.cuda.synchronize()
+        t_inf = time.perf_counter() - t0
         r = solve(A, start=X, seed=1)
         torch.cuda.synchronize()
         t_learned = time.perf_counter() - t0
         row = {"graph": desc, "fallback": X is None,
-               "learned_spmm": r.spmm_calls, "learned_s": t_learned,
+               "learned_spmm": r.spmm_calls, "learned_s": t_learned, "inference_s": t_inf,
                "random_spmm": float(np.median([q.spmm_calls for q in rand])),
                "random_s": float(np.median(t_rand)),
-               "learned_ok": r.status == F.FE_OK}
+               "learned_ok": r.status == F.FE_OK,
+               "random_ok": all(q.status == F.FE_OK for q in rand)}
         rows.append(row)
         log(f"[eval] {desc}: learned {row['learned_spmm']} products {t_learned*1e3:.1f} ms, "
             f"random {row['random_spmm']:.0f} products {row['random_s']*1e3:.1f} ms")
-    ratio_spmm = [r["learned_spmm"] / r["random_spmm"] for r in rows]
-    ratio_t = [r["learned_s"] / r["random_s"] for r in rows]
-    summary = {"heldout": heldout, "median_spmm_ratio": float(np.median(ratio_spmm)),
-               "median_time_ratio": float(np.median(ratio_t)),
-               "frac_improved_spmm": float(np.mean([x < 1 for x in ratio_spmm])),
-               "fallbacks": int(sum(r["fallback"] for r in rows)), "rows": rows}
+    def stats(sel):
+        if not sel:
+            return {}
+        rs = [r["learned_spmm"] / r["random_spmm"] for r in sel]
+        rt = [r["learned_s"] / r["random_s"] for r in sel]
+        return {"graphs": len(sel), "median_spmm_ratio": float(np.median(rs)),
+                "median_time_ratio": float(np.median(rt)),
+                "total_spmm_ratio": float(sum(r["learned_spmm"] for r in sel)
+                                          / sum(r["random_spmm"] for r in sel)),
+                "total_time_ratio": float(sum(r["learned_s"] for r in sel)
+                                          / sum(r["random_s"] for r in sel)),
+                "frac_improved_spmm": float(np.mean([x < 1 for x in rs])),
+                "median_inference_ms": 1e3 * float(np.median([r["inference_s"] for r in sel]))}
+    # graphs where a solve hit the restart cap carry no time-to-tolerance
+    ok = [r for r in rows if r["learned_ok"] and r["random_ok"]]
+    summary = {"heldout": heldout, "both_converged": len(ok), **stats(ok),
+               "chung_lu": stats([r for r in ok if r["graph"].startswith("chung_lu")]),
+               "sbm": stats([r for r in ok if r["graph"].startswith("sbm")]),
+               "fallbacks": int(sum(r["fallback"] for r in rows)),
+               "learned_not_converged": int(sum(not r["learned_ok"] for r in rows)),
+               "random_not_converged": int(sum(not r["random_ok"] for r in rows)), "rows": rows}
     return summary
 
 
@@ -159,16 +220,28 @@ def main():
     t.add_argument("--init-seed", type=int, default=0)
     t.add_argument("--max-log2n", type=int, default=18)
     t.add_argument("--out", default=DEFAULT_WEIGHTS)
+    t.add_argument("--compute", default="bf16", choices=["bf16", "f32"])
+    t.add_argument("--clip", type=float, default=1.0, help="global gradient-norm clip (0: off)")
+    t.add_argument("--val", type=int, default=100, help="validation graphs")
+    t.add_argument("--val-seed", type=int, default=9000)
+    t.add_argument("--label-budget", type=float, default=1e9, help="seconds")
+    t.add_argument("--time-budget", type=float, default=1e9, help="seconds, whole run")
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=DEFAULT_WEIGHTS)
     e.add_argument("--heldout", type=int, default=200)
     e.add_argument("--max-log2n", type=int, default=18)
+    e.add_argument("--first-seed", type=int, default=3000)
+    e.add_argument("--rows", default=None, help="write the per-graph rows as JSON here")
     args = ap.parse_args()
     _torch().cuda.set_device(0)
     if args.cmd == "train":
         train(args)
     else:
-        s = evaluate(args.weights, args.heldout, max_log2n=args.max_log2n)
+        s = evaluate(args.weights, args.heldout, first_seed=args.first_seed,
+                     max_log2n=args.max_log2n, log=lambda m: print(m, flush=True))
+        if args.rows:
+            with open(args.rows, "w") as f:
+                json.dump(s, f, indent=1)
         print(json.dumps({k: v for k, v in s.items() if k != "rows"}), flush=True)
 
 

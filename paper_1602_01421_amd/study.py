@@ -1,0 +1,197 @@
+"""Precision comparison and the one-GPU large-graph run (GPU; library calls only).
+
+precision
+    R-MAT graph (default scale 24, edge factor 16, a/b/c/d .57/.19/.19/.05),
+    nev 8, block 8, m 64.  An FP64-storage solve (tol 1e-10) is the reference;
+    then FP32 storage (tol 1e-6), BF16 storage (tol 1e-3: BF16 cannot hold a
+    basis whose residuals reach 1e-6) and mixed BF16->FP32 storage (tol 1e-6).
+    Per precision: largest eigenvalue error relative to the FP64 solve, the
+    solver's own explicit FP64 residuals, products, restarts, wall time; plus
+    the product alone at block 8 in FP32 and BF16.
+
+large
+    R-MAT scale 27 (134M vertices, ~4.2e9 stored nonzeros, int64 offsets),
+    nev 8, block 8, m 48: the product alone at block 8 (FP32), the plain FP32
+    solve from a random start, the learned-start mixed-precision solve
+    (network inference on the GPU included in its time; the network's random
+    inputs drawn on the GPU) and an FP64-storage reference solve.
+
+Both print one JSON line; progress goes to stdout as the steps finish.
+
+    python -m paper_1602_01421_amd.study precision --scale 24
+    python -m paper_1602_01421_amd.study large --scale 27 --weights W.npy
+"""
+from __future__ import annotations
+
+import argparse
+import gc
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def build_rmat(F, scale: int):
+    import fe_synth as S
+    t0 = time.perf_counter()
+    n, s, d = S.rmat_edges(scale, seed=scale)
+    t_gen = time.perf_counter() - t0
+    _log(f"[study] generated R-MAT scale {scale}: {len(s)} samples in {t_gen:.1f} s")
+    t0 = time.perf_counter()
+    A = F.fe_csr_build(n, s, d, F.FE_GRAPH_DEFAULT | F.FE_RELABEL_BY_DEGREE)
+    t_build = time.perf_counter() - t0
+    del s, d
+    gc.collect()
+    _log(f"[study] CSR n={A.n} nnz={A.nnz} max_deg={A.max_deg} built in {t_build:.1f} s")
+    return A, {"gen_s": t_gen, "build_s": t_build}
+
+
+def time_spmm(F, A, b, dtype, reps=10):
+    """Mean duration (s) of one product at width b, HIP events on its stream."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    X = torch.randn((A.n, b), generator=g, device="cuda", dtype=torch.float32).to(dtype)
+    Y = torch.empty_like(X)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        F.fe_spmm(A, X, Y, stream=st)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            F.fe_spmm(A, X, Y, stream=st)
+        e1.record(st)
+    st.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    es = X.element_size()
+    algo = 4.0 * A.nnz + 8.0 * (A.n + 1) + 2.0 * A.n * b * es
+    del X, Y
+    return {"b": b, "dtype": str(dtype).replace("torch.", ""), "ms": t * 1e3,
+            "gedge_col_s": A.nnz * b / t / 1e9, "gbs": algo / t / 1e9,
+            "frac": algo / t / 1e9 / HBM_PEAK_GBS}
+
+
+def run_solve(F, A, label, ref=None, **kw):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = F.fe_krylov_schur(A, want_vectors=False, **kw)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    row = {"run": label, "status": int(r.status), "seconds": t, "restarts": r.restarts,
+           "spmm_calls": r.spmm_calls, "spmm_calls_bf16": r.spmm_calls_low,
+           "switch_restart": r.switch_restart, "refills": r.refills,
+           "max_resid": float(np.max(r.resid)), "evals": [float(x) for x in r.evals]}
+    if ref is not None:
+        row["max_eval_rel_err_vs_f64"] = float(np.max(np.abs(r.evals - ref) / np.abs(ref)))
+    _log(f"[study] {label}: status {r.status} {t:.2f} s, {r.spmm_calls} products, "
+         f"max resid {row['max_resid']:.2e}"
+         + (f", eval err {row['max_eval_rel_err_vs_f64']:.2e}" if ref is not None else ""))
+    return row, r
+
+
+def precision(args):
+    from . import fe as F
+    import torch
+    A, info = build_rmat(F, args.scale)
+    nev, b, m = 8, args.block, args.m
+    out = {"study": "precision", "graph": f"rmat{args.scale}", "n": A.n, "nnz": A.nnz,
+           "nev": nev, "block": b, "m": m, **info}
+    out["spmm"] = [time_spmm(F, A, b, torch.float32), time_spmm(F, A, b, torch.bfloat16)]
+    _log(f"[study] product b={b}: " + ", ".join(f"{x['dtype']} {x['ms']:.2f} ms" for x in out["spmm"]))
+    ref_row, ref = run_solve(F, A, "f64", nev=nev, block=b, m=m, tol=1e-10,
+                             dtype=torch.float64, seed=1)
+    rows = [ref_row]
+    rows.append(run_solve(F, A, "f32", ref.evals, nev=nev, block=b, m=m, tol=1e-6,
+                          dtype=torch.float32, seed=1)[0])
+    rows.append(run_solve(F, A, "bf16", ref.evals, nev=nev, block=b, m=m, tol=1e-3,
+                          dtype=torch.bfloat16, seed=1, max_restarts=args.bf16_restarts)[0])
+    rows.append(run_solve(F, A, "mixed_bf16_f32", ref.evals, nev=nev, block=b, m=m, tol=1e-6,
+                          dtype=torch.float32, seed=1, mixed=True)[0])
+    out["solves"] = rows
+    print(json.dumps(out), flush=True)
+
+
+def large(args):
+    from . import fe as F
+    from .learned import learned_start
+    import torch
+    A, info = build_rmat(F, args.scale)
+    nev, b, m = 8, args.block, args.m
+    out = {"study": "large", "graph": f"rmat{args.scale}", "n": A.n, "nnz": A.nnz,
+           "max_deg": A.max_deg, "nev": nev, "block": b, "m": m, **info}
+    out["spmm"] = [time_spmm(F, A, b, torch.float32, reps=args.spmm_reps)]
+    x = out["spmm"][0]
+    _log(f"[study] product b={b} FP32: {x['ms']:.2f} ms, {x['gedge_col_s']:.0f} GEdge*col/s, "
+         f"{x['gbs']:.0f} GB/s ({100 * x['frac']:.1f}% of 8 TB/s)")
+    gc.collect()
+    torch.cuda.empty_cache()
+    ref_row, ref = run_solve(F, A, "f64_reference", nev=nev, block=b, m=m, tol=1e-10,
+                             dtype=torch.float64, seed=2)
+    rows = [ref_row]
+    torch.cuda.empty_cache()
+    rows.append(run_solve(F, A, "f32_random_start", ref.evals, nev=nev, block=b, m=m,
+                          tol=1e-6, dtype=torch.float32, seed=1)[0])
+    torch.cuda.empty_cache()
+    if args.weights:
+        net = F.Gnn(seed=0, compute="bf16")
+        net.set_params(np.load(args.weights))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = torch.Generator(device="cuda")
+        g.manual_seed(args.scale)
+        z = torch.randn((A.n, 15), generator=g, device="cuda", dtype=torch.float32)
+        X = learned_start(net, A, z, torch.float32)
+        del z
+        net.close()  # releases the inference workspace (4 x n x 64 floats)
+        torch.cuda.synchronize()
+        t_inf = time.perf_counter() - t0
+        _log(f"[study] network inference {t_inf:.2f} s (fallback: {X is None})")
+        row, _ = run_solve(F, A, "learned_start_mixed", ref.evals, nev=nev, block=b, m=m,
+                           tol=1e-6, dtype=torch.float32, seed=1, start=X, mixed=True)
+        row["inference_s"] = t_inf
+        row["end_to_end_s"] = t_inf + row["seconds"]
+        row["fallback"] = X is None
+        rows.append(row)
+        del X
+        torch.cuda.empty_cache()
+        rows.append(run_solve(F, A, "random_start_mixed", ref.evals, nev=nev, block=b, m=m,
+                              tol=1e-6, dtype=torch.float32, seed=1, mixed=True)[0])
+    out["solves"] = rows
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    p = sub.add_parser("precision")
+    p.add_argument("--scale", type=int, default=24)
+    p.add_argument("--block", type=int, default=8)
+    p.add_argument("--m", type=int, default=64)
+    p.add_argument("--bf16-restarts", type=int, default=200)
+    q = sub.add_parser("large")
+    q.add_argument("--scale", type=int, default=27)
+    q.add_argument("--block", type=int, default=8)
+    q.add_argument("--m", type=int, default=48)
+    q.add_argument("--weights", default=None)
+    q.add_argument("--spmm-reps", type=int, default=10)
+    args = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    {"precision": precision, "large": large}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    main()

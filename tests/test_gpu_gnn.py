@@ -93,6 +93,23 @@ def test_adam_step_matches_oracle(fe):
     assert np.allclose(p1, want, rtol=1e-5, atol=1e-7)
 
 
+def test_adam_clipped_step_matches_oracle(fe):
+    A, rp, ci, z, V = case(fe, n=3000, seed=12)
+    net = fe.Gnn(seed=6)
+    p0 = net.get_params().astype(np.float64)
+    zt = torch.tensor(z, dtype=torch.float32, device="cuda")
+    Vt = torch.tensor(V, dtype=torch.float32, device="cuda")
+    _, g = net.backward(A, zt, Vt, want_grads=True)
+    clip = 0.1 * float(np.linalg.norm(g))  # active: scales the step's gradient by 0.1
+    net.adam(1e-2, clip=clip)
+    torch.cuda.synchronize()
+    p1 = net.get_params().astype(np.float64)
+    want = G.adam_step({"p": p0.copy()}, {"p": g.astype(np.float64)}, {}, lr=1e-2, clip=clip)["p"]
+    assert np.allclose(p1, want, rtol=1e-5, atol=1e-7)
+    with pytest.raises(fe.FeError):
+        net.adam(1e-2, clip=-1.0)
+
+
 def test_training_reduces_loss(fe):
     """A few Adam steps on one graph lower the loss (sanity of the whole loop)."""
     A, rp, ci, z, V = case(fe, n=4000, seed=13)

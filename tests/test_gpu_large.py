@@ -1,0 +1,90 @@
+"""R-MAT scale 27 at full size: 134M vertices, ~4.2e9 stored nonzeros.
+
+Opt-in (FE_LARGE_TESTS=1; about five minutes, ~80 GB of host memory): the
+graph alone takes minutes to generate and build.  Bars: the FP32 product at
+block 8 on sampled rows (all hub rows, the tail, random rows) within
+1e-5 * sum|X| of the oracle's rows taken straight from the edge stream; an
+FP32-storage solve (nev 8, block 8, m 48, tol 1e-6) whose eigenvalues match
+an FP64-storage solve to 1e-8 relative, with explicit residuals <= 1e-6; and
+on sampled rows, every entry of A x - theta x computed by the oracle stays
+within the solver's reported residual norm (plus the FP32 rounding of x).
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import fe_synth as S
+import oracle as O
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(os.environ.get("FE_LARGE_TESTS") != "1",
+                                 reason="scale-27 graph: set FE_LARGE_TESTS=1 (minutes)")]
+
+SCALE = int(os.environ.get("FE_LARGE_SCALE", "27"))
+
+
+def say(msg):
+    print(f"[large] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def graph(fe):
+    t0 = time.perf_counter()
+    n, s, d = S.rmat_edges(SCALE, seed=SCALE)
+    say(f"scale {SCALE}: {len(s)} samples ({time.perf_counter() - t0:.0f} s)")
+    A = fe.fe_csr_build(n, s, d, fe.FE_GRAPH_DEFAULT | fe.FE_RELABEL_BY_DEGREE)
+    say(f"CSR n={A.n} nnz={A.nnz} max_deg={A.max_deg} ({time.perf_counter() - t0:.0f} s)")
+    assert A.nnz > 2 ** 31 or SCALE < 27  # the scale-27 graph needs 64-bit offsets
+    return A, n, s, d
+
+
+def sample_rows(n, perm, seed):
+    rng = np.random.default_rng(seed)
+    new_rows = np.unique(np.concatenate([np.arange(64), rng.integers(0, n, 2000),
+                                         np.arange(n - 16, n)]))
+    return new_rows, perm[new_rows]
+
+
+def test_spmm_sampled_rows(fe, graph):
+    A, n, s, d = graph
+    perm = A.perm()
+    X = torch.randn((n, 8), generator=torch.Generator().manual_seed(1), dtype=torch.float32)
+    Xd = X[torch.from_numpy(perm).long()].cuda()  # internal (relabelled) order
+    Y = fe.fe_spmm(A, Xd)
+    new_rows, old_rows = sample_rows(n, perm, 8)
+    got = Y[torch.from_numpy(new_rows).cuda()].double().cpu().numpy()
+    del Xd, Y
+    Xo = X.double().numpy()
+    order = np.argsort(old_rows)
+    want = O.spmm_rows_from_edges(n, s, d, Xo, old_rows[order])
+    absum = O.spmm_rows_from_edges(n, s, d, np.abs(Xo), old_rows[order])
+    say(f"sampled {len(new_rows)} rows of the product")
+    assert np.all(np.abs(got[order] - want) <= 1e-5 * absum + 1e-30)
+
+
+def test_fp32_solve_vs_fp64(fe, graph):
+    A, n, s, d = graph
+    t0 = time.perf_counter()
+    r32 = fe.fe_krylov_schur(A, 8, 8, 48, 1e-6, dtype=torch.float32, seed=1)
+    say(f"FP32 solve {time.perf_counter() - t0:.1f} s, {r32.spmm_calls} products")
+    X = r32.evecs.cpu().double().numpy()  # original vertex order
+    del r32.evecs
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    r64 = fe.fe_krylov_schur(A, 8, 8, 48, 1e-10, dtype=torch.float64, seed=2, want_vectors=False)
+    say(f"FP64 solve {time.perf_counter() - t0:.1f} s, {r64.spmm_calls} products")
+    assert r32.status == fe.FE_OK and r64.status == fe.FE_OK
+    assert np.all(np.abs(r32.evals - r64.evals) <= 1e-8 * np.abs(r64.evals))
+    assert r32.resid.max() <= 1e-6
+    rows = np.sort(np.random.default_rng(9).choice(n, 3000, replace=False))
+    rows = np.union1d(rows, np.argsort(-np.abs(X[:, 0]))[:64])  # where x_1 is largest
+    AX = O.spmm_rows_from_edges(n, s, d, X, rows)
+    AabsX = O.spmm_rows_from_edges(n, s, d, np.abs(X), rows)
+    R = AX - X[rows] * r32.evals
+    norm = r32.resid * np.abs(r32.evals) * np.linalg.norm(X, axis=0)
+    slack = 2.0 ** -23 * (AabsX + np.abs(r32.evals) * np.abs(X[rows]))
+    say(f"sampled residual entries: max ratio {np.max(np.abs(R) / (norm + slack)):.3f}")
+    assert np.all(np.abs(R) <= 1.001 * norm + slack)

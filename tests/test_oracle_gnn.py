@@ -115,3 +115,16 @@ def test_adam_constant_gradient():
         p = G.adam_step(p, g, st, lr=0.01)
     # bias-corrected Adam on a constant gradient moves by lr * sign(g) each step
     assert np.allclose(p["w"], -0.1 * np.sign(g["w"]), rtol=1e-6)
+
+
+def test_adam_global_norm_clipping():
+    g = {"a": np.array([3.0, 0.0]), "b": np.array([[4.0]])}  # global norm 5
+    st = {}
+    p = G.adam_step({"a": np.zeros(2), "b": np.zeros((1, 1))}, g, st, lr=0.01, clip=1.0)
+    # first moment after one step: (1 - beta1) * g * clip / ||g||
+    assert np.allclose(st["m_a"], 0.1 * np.array([0.6, 0.0]), rtol=1e-15)
+    assert np.allclose(st["m_b"], 0.1 * np.array([[0.8]]), rtol=1e-15)
+    assert np.allclose(st["v_b"], 0.001 * 0.64, rtol=1e-12)
+    st2 = {}
+    G.adam_step({"a": np.zeros(2), "b": np.zeros((1, 1))}, g, st2, lr=0.01, clip=10.0)
+    assert np.allclose(st2["m_a"], 0.1 * g["a"], rtol=1e-15)  # norm below clip: unchanged

@@ -118,6 +118,22 @@ def test_spmm_brute_force_integer_exact():
     assert np.array_equal(Y[::37], ref)
 
 
+def test_spmm_rows_from_edges_brute_force():
+    """Sampled rows straight from an edge stream (with repeats and self-loops)
+    equal rows of the dense brute-force A X."""
+    n, s, d = S.chung_lu_edges(300, alpha=2.1, mean_deg=12, seed=5)
+    A = np.zeros((n, n))
+    for u, v in zip(s.tolist(), d.tolist()):
+        if u != v:
+            A[u, v] = A[v, u] = 1.0
+    X = S.small_ints((n, 5), seed=6)
+    rows = np.array([0, 1, 7, 150, 298, 299])
+    got = O.spmm_rows_from_edges(n, s, d, X, rows)
+    assert np.array_equal(got, (A @ X)[rows])
+    hub = int(np.argmax(A.sum(1)))
+    assert np.array_equal(O.spmm_rows_from_edges(n, s, d, X, np.array([hub])), (A @ X)[[hub]])
+
+
 def test_spmm_linearity_symmetry_threads():
     n, rp, ci = csr(S.rmat_edges(12, seed=7))
     X, Z = S.normal((n, 3), seed=1), S.normal((n, 3), seed=2)
