@@ -112,6 +112,62 @@ def cpu_baseline(n, s, d, nnz, budget_s=25.0):
                       f"{t:.1f} s (oracle CSR build {t_csr:.1f} s not timed)"}
 
 
+def learned_vs_random(P, A, stream, weights, tol, m=48, seeds=3):
+    """Time to 8 eigenpairs from the learned start block vs random starts.
+
+    Block 8 (the network's 8 output columns), FP32 storage.  The learned time
+    is end to end: drawing the network's N(0,1) inputs on the GPU, inference,
+    the fallback check and the solve.
+    """
+    import numpy as np
+    import torch
+    from paper_1602_01421_amd.learned import learned_start
+    net = P.Gnn(seed=0, compute="bf16")
+    net.set_params(np.load(weights))
+
+    def solve(start=None, seed=1):
+        return P.fe_krylov_schur(A, 8, 8, m, tol, dtype=torch.float32, start=start, seed=seed,
+                                 stream=stream, want_vectors=False)
+
+    solve(seed=99)  # warm-up at this block width
+    rand = []
+    for k in range(seeds):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = solve(seed=1 + k)
+        torch.cuda.synchronize()
+        rand.append((time.perf_counter() - t0, r.spmm_calls, r.status))
+    learned = []
+    for k in range(seeds):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1 + k)
+        z = torch.randn((A.n, 15), generator=g, device="cuda", dtype=torch.float32)
+        X = learned_start(net, A, z, torch.float32)
+        torch.cuda.synchronize()
+        t_inf = time.perf_counter() - t0
+        r = solve(start=X, seed=1 + k)
+        torch.cuda.synchronize()
+        learned.append((time.perf_counter() - t0, r.spmm_calls, r.status, t_inf, X is None))
+        del z, X
+    net.close()
+    med = lambda xs: float(np.median(xs))  # noqa: E731
+    res = {"block": 8, "m": m, "tol": tol, "dtype": "f32", "seeds": seeds,
+           "random_s": med([x[0] for x in rand]), "random_spmm": med([x[1] for x in rand]),
+           "learned_s": med([x[0] for x in learned]),
+           "learned_spmm": med([x[1] for x in learned]),
+           "inference_s": med([x[3] for x in learned]),
+           "fallbacks": int(sum(x[4] for x in learned)),
+           "all_converged": all(x[2] == 0 for x in rand + learned)}
+    res["time_ratio"] = res["learned_s"] / res["random_s"]
+    res["spmm_ratio"] = res["learned_spmm"] / res["random_spmm"]
+    log(f"time to 8 eigs (b=8, m={m}, FP32): random {res['random_s']:.3f} s / "
+        f"{res['random_spmm']:.0f} products, learned {res['learned_s']:.3f} s / "
+        f"{res['learned_spmm']:.0f} products (inference {res['inference_s']*1e3:.1f} ms)")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +179,9 @@ def main():
     ap.add_argument("--mixed", action="store_true",
                     help="BF16 storage widened to FP32 when BF16 stalls (mixed-precision solve)")
     ap.add_argument("--sweep", default="1,2,4,8,16", help="SpMM-only widths (FP32)")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1602_01421_amd", "weights",
+                                                      "gnn_start.npy"),
+                    help="learned start-block weights ('' to skip the comparison)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--spmm-reps", type=int, default=50)
     args = ap.parse_args()
@@ -227,6 +286,8 @@ def main():
         "spmm_sweep": sweep,
         "build_s": t_build,
     }
+    if args.weights and os.path.exists(args.weights):
+        out["learned_vs_random"] = learned_vs_random(P, A, stream, args.weights, tol)
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(n, s, d, A.nnz)

@@ -146,6 +146,23 @@ fe_status fe_block_update(void *W, int64_t n, int32_t b, const void *V, int32_t 
                           int64_t blk_stride, const double *C, double alpha, double beta,
                           fe_dtype dt, void *hip_stream);
 
+/*
+ * The middle step of classical Gram-Schmidt twice (the reorthogonalisation
+ * of Algorithm 1's step (1)) fused into one pass over V:
+ *   W <- W - V C            (C: device FP64 k x b, k = nblk*b; FP64
+ *                            arithmetic, rounded to dt)
+ *   Cout = [V W]^T W        (device FP64 (k + b) x b row-major, taken from
+ *                            the rounded W; rows 0..k-1 are V^T W, the last
+ *                            b rows W^T W)
+ * Equal to fe_block_update (alpha -1, beta 1) followed by fe_gram over the
+ * nblk blocks plus W, up to the order of the FP64 sums.  V and W as in
+ * fe_gram; W must not overlap V.  Errors: FE_EINVAL (sizes, NULL, overlap),
+ * FE_EUNSUPPORTED (b not in {1,2,4,8,16} or k > 64), FE_ENOMEM, FE_EDEVICE.
+ */
+fe_status fe_block_update_gram(void *W, int64_t n, int32_t b, const void *V, int32_t nblk,
+                               int64_t blk_stride, const double *C, double *Cout, fe_dtype dt,
+                               void *hip_stream);
+
 /* Options of fe_krylov_schur.  Zero-initialise, then set what you need. */
 typedef struct {
   fe_dtype dt;           /* storage dtype of the subspace (default FE_F64 = 0) */

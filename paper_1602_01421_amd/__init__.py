@@ -7,6 +7,7 @@ missing or no GPU is present, the entry points raise.
 from .fe import (  # noqa: F401
     EXPORTED, FE_BF16, FE_DEDUPE, FE_DROP_SELF, FE_EBREAKDOWN, FE_EDEVICE, FE_EINVAL, FE_ENOCONV,
     FE_ENOMEM, FE_EUNSUPPORTED, FE_F32, FE_F64, FE_GRAPH_DEFAULT, FE_OK, FE_RELABEL_BY_DEGREE,
-    FE_SYMMETRIZE, GNN_SHAPES, LIB_PATH, Csr, FeError, Gnn, KsResult, gnn_flatten, gnn_unflatten, fe_block_update, fe_csr_build,
+    FE_SYMMETRIZE, GNN_SHAPES, LIB_PATH, Csr, FeError, Gnn, KsResult, gnn_flatten, gnn_unflatten, fe_block_update, fe_block_update_gram,
+    fe_csr_build,
     fe_csr_from_csr, fe_dense_symeig, fe_gram, fe_krylov_schur, fe_spmm, lib, torch_dtype,
     version)

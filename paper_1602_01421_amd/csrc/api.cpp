@@ -411,4 +411,29 @@ fe_status fe_block_update(void* W, int64_t n, int32_t b, const void* V, int32_t 
   return update_launch(W, n, b, V, nblk, stride, C, alpha, beta, dt, (hipStream_t)stream);
 }
 
+fe_status fe_block_update_gram(void* W, int64_t n, int32_t b, const void* V, int32_t nblk,
+                               int64_t stride, const double* C, double* Cout, fe_dtype dt,
+                               void* stream) {
+  FE_TRY(check_blocks("fe_block_update_gram", V, nblk, stride, n, b, dt));
+  if (!W || !C || !Cout) return fail(FE_EINVAL, "fe_block_update_gram: NULL argument");
+  if (!(b == 1 || b == 2 || b == 4 || b == 8 || b == 16) || nblk * b > 64)
+    return fail(FE_EUNSUPPORTED, "fe_block_update_gram: needs b in {1,2,4,8,16} and k <= 64");
+  const size_t es = dtype_size(dt);
+  const size_t vbytes = ((size_t)(nblk - 1) * stride + (size_t)n * b) * es;
+  if (overlap(W, (size_t)n * b * es, V, vbytes))
+    return fail(FE_EINVAL, "fe_block_update_gram: W overlaps V");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t np = gram_partials_doubles(n, nblk * b + b, b);
+  double* part = nullptr;
+  hipError_t e = hipMallocAsync((void**)&part, np * sizeof(double), s);
+  if (e != hipSuccess)
+    return fail(FE_ENOMEM, "fe_block_update_gram: hipMallocAsync: %s", hipGetErrorString(e));
+  fe_status st = update_gram_launch(W, n, b, V, nblk, stride, C, Cout, part, dt, s);
+  hipError_t e2 = hipFreeAsync(part, s);
+  if (st != FE_OK) return st;
+  if (e2 != hipSuccess)
+    return fail(FE_EDEVICE, "fe_block_update_gram: hipFreeAsync: %s", hipGetErrorString(e2));
+  return FE_OK;
+}
+
 }  // extern "C"

@@ -243,6 +243,147 @@ __global__ __launch_bounds__(256) void update_generic(T* __restrict__ W, int64_t
   W[e] = to_storage<T, double>(acc);
 }
 
+// ------------------------------------------------- fused update + Gram
+// The middle of a classical Gram-Schmidt sweep in one pass over V:
+//   W' = W - V C          (C: the first k rows of the previous Gram, FP64)
+//   partial sums of [V W']^T W'   ((k + B) x B, the Gram kernel's layout)
+// W' is rounded to T, written back, and the Gram uses the ROUNDED values, so
+// the result equals a separate update followed by a Gram up to the order of
+// the sums.  Tiles of kUgRows rows of [V W] are staged in LDS as FP64 (exact
+// widening of every storage type); arithmetic is FP64.  Each workgroup walks
+// a fixed row range; its four wavefronts take interleaved rows and their
+// partials are added in wavefront order (deterministic).
+constexpr int kUgRows = 64;
+constexpr int kUgWG = 256;
+
+int ug_sets(int64_t n) {  // up to 8 resident workgroups per CU on 256 CUs
+  const int64_t by_rows = (n + 4 * kUgRows - 1) / (4 * kUgRows);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(2048, by_rows));
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(kUgWG) void update_gram_kernel(T* __restrict__ W, int64_t n,
+                                                            const T* __restrict__ V, int32_t nblk,
+                                                            int64_t stride,
+                                                            const double* __restrict__ C,
+                                                            int64_t rows_per_wg,
+                                                            double* __restrict__ partials) {
+  constexpr int VEC = (B * sizeof(T) >= 16) ? 16 / sizeof(T) : B;
+  constexpr int NU = (kUgRows * B + kUgWG - 1) / kUgWG;  // update outputs per thread
+  constexpr int NW = kUgWG / 64;                          // wavefronts
+  extern __shared__ double smem[];
+  const int k = nblk * B, kk = k + B, ld = kk | 1;  // odd row stride spreads LDS banks
+  double* Cs = smem;              // k x B
+  double* X = smem + k * B;       // kUgRows x ld: [V row | W row], FP64 (exact widening)
+  double* red = X;                // reused at the end: NW x (kk x B) wave partials
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  for (int i = t; i < k * B; i += kUgWG) Cs[i] = C[i];
+  // Gram outputs: lane owns columns p = lane and lane + 64 (kk <= 80) and all
+  // B columns q of W'; the wavefronts split each tile's rows (r = wave mod NW)
+  double acc[2][B];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int q = 0; q < B; ++q) acc[h][q] = 0.0;
+  const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r_end = min(n, r_begin + rows_per_wg);
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kUgRows) {
+    const int nr = (int)min((int64_t)kUgRows, r_end - r0);
+    __syncthreads();  // Cs staged; the previous tile fully consumed
+    const int per = nr * B / VEC;  // vector chunks per block row-range
+    for (int c = t; c < (nblk + 1) * per; c += kUgWG) {
+      const int j = c / per, off = (c - j * per) * VEC;
+      const T* src = (j < nblk ? V + (int64_t)j * stride : W) + r0 * B + off;
+      double v[VEC];
+      load_vec<T, VEC>(src, v);
+      const int r = off / B, col = j * B + off % B;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) X[r * ld + col + e] = v[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+      const int e = t + i * kUgWG;
+      if (e < nr * B) {
+        const int r = e / B, q = e % B;
+        const double* xr = X + r * ld;
+        // same order as the update kernel (sum of V C first, then W), so W'
+        // is bitwise what fe_block_update(alpha -1, beta 1) produces
+        double a = 0.0;
+        for (int p = 0; p < k; ++p) a = fma(xr[p], -Cs[p * B + q], a);
+        a = fma(1.0, xr[k + q], a);
+        const T o = to_storage<T, double>(a);
+        W[(r0 + r) * B + q] = o;
+        X[r * ld + k + q] = load_f64(&o);  // only this thread reads this entry
+      }
+    }
+    __syncthreads();
+    for (int r = wave; r < nr; r += NW) {
+      const double* xr = X + r * ld;
+      double w[B];
+#pragma unroll
+      for (int q = 0; q < B; ++q) w[q] = xr[k + q];  // same address in every lane
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int p = lane + 64 * h;
+        const double x = xr[p < kk ? p : 0];
+#pragma unroll
+        for (int q = 0; q < B; ++q) acc[h][q] = fma(x, w[q], acc[h][q]);
+      }
+    }
+  }
+  // wavefront partials added in wavefront order (deterministic)
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int p = lane + 64 * h;
+    if (p < kk)
+#pragma unroll
+      for (int q = 0; q < B; ++q) red[(wave * kk + p) * B + q] = acc[h][q];
+  }
+  __syncthreads();
+  double* out = partials + (int64_t)blockIdx.x * kk * B;
+  for (int e = t; e < kk * B; e += kUgWG) {
+    double sum = red[e];
+    for (int w2 = 1; w2 < NW; ++w2) sum += red[w2 * kk * B + e];
+    out[e] = sum;
+  }
+}
+
+template <typename T>
+fe_status update_gram_t(void* W, int64_t n, int32_t b, const void* V, int32_t nblk,
+                        int64_t stride, const double* C, double* Cout, double* partials,
+                        hipStream_t s) {
+  const int k = nblk * b, kk = k + b, ld = kk | 1;
+  if (k > 64 || nblk < 1)
+    return fail(FE_EUNSUPPORTED, "update_gram: %d basis columns (1 block .. 64 columns)", k);
+  const int gx = ug_sets(n);
+  int64_t rows_per_wg = (n + gx - 1) / gx;
+  rows_per_wg = (rows_per_wg + kUgRows - 1) / kUgRows * kUgRows;
+  // Cs + the tile; the tile area is reused for the 4 wavefronts' partials
+  const size_t lds = sizeof(double) * ((size_t)k * b + std::max<size_t>((size_t)kUgRows * ld,
+                                                                         (size_t)4 * kk * b));
+  T* Wp = static_cast<T*>(W);
+  const T* Vp = static_cast<const T*>(V);
+#define FE_UG(BB)                                                                              \
+  case BB:                                                                                     \
+    hipLaunchKernelGGL((update_gram_kernel<T, BB>), dim3(gx), dim3(kUgWG), lds, s, Wp, n, Vp,   \
+                       nblk, stride, C, rows_per_wg, partials);                                \
+    break;
+  switch (b) {
+    FE_UG(1) FE_UG(2) FE_UG(4) FE_UG(8) FE_UG(16)
+    default:
+      return fail(FE_EUNSUPPORTED, "update_gram: block %d not in {1,2,4,8,16}", b);
+  }
+#undef FE_UG
+  FE_HIP(hipGetLastError());
+  const int len = kk * b;
+  hipLaunchKernelGGL(reduce_partials, dim3((len + 63) / 64), dim3(1024), 0, s, partials, gx, len,
+                     1.0, Cout);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
 template <typename T>
 fe_status update_t(void* W, int64_t n, int32_t b, const void* V, int32_t nblk, int64_t stride,
                    const double* C, double alpha, double beta, hipStream_t s) {
@@ -503,7 +644,18 @@ fe_status convert_from(void* dst, fe_dtype ddt, const S* src, int64_t count, hip
 
 // ------------------------------------------------------------- launchers
 size_t gram_partials_doubles(int64_t n, int32_t k, int32_t b) {
-  return (size_t)gram_sets(n) * (size_t)k * (size_t)b;
+  return (size_t)std::max(gram_sets(n), ug_sets(n)) * (size_t)k * (size_t)b;
+}
+
+fe_status update_gram_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk,
+                             int64_t stride, const double* C, double* Cout, double* partials,
+                             fe_dtype dt, hipStream_t s) {
+  switch (dt) {
+    case FE_F64: return update_gram_t<double>(W, n, b, V, nblk, stride, C, Cout, partials, s);
+    case FE_F32: return update_gram_t<float>(W, n, b, V, nblk, stride, C, Cout, partials, s);
+    case FE_BF16: return update_gram_t<bf16_t>(W, n, b, V, nblk, stride, C, Cout, partials, s);
+  }
+  return fail(FE_EINVAL, "update_gram: bad dtype");
 }
 
 fe_status gram_launch(const void* V, int32_t nblk, int64_t stride, const void* W, int64_t n,

@@ -82,6 +82,12 @@ size_t gram_partials_doubles(int64_t n, int32_t k, int32_t b);
 fe_status gram_launch(const void* V, int32_t nblk, int64_t blk_stride, const void* W, int64_t n,
                       int32_t b, fe_dtype dt, double alpha, double* C, double* partials,
                       hipStream_t s);
+// W <- W - V C (C: k x b FP64, k = nblk*b <= 64, b in {1,2,4,8,16}) and, in
+// the same pass, Cout ((k+b) x b) = [V W']^T W' of the rounded result;
+// partials sized by gram_partials_doubles(n, k + b, b).
+fe_status update_gram_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk,
+                             int64_t blk_stride, const double* C, double* Cout, double* partials,
+                             fe_dtype dt, hipStream_t s);
 fe_status update_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk,
                         int64_t blk_stride, const double* C, double alpha, double beta,
                         fe_dtype dt, hipStream_t s);

@@ -23,7 +23,7 @@ FE_GRAPH_DEFAULT = FE_SYMMETRIZE | FE_DEDUPE | FE_DROP_SELF
 
 EXPORTED = ("fe_last_error", "fe_version", "fe_csr_build", "fe_csr_from_csr", "fe_csr_info",
             "fe_csr_perm", "fe_csr_export", "fe_csr_free", "fe_spmm", "fe_gram",
-            "fe_block_update", "fe_krylov_schur", "fe_dense_symeig", "fe_gnn_param_count",
+            "fe_block_update", "fe_block_update_gram", "fe_krylov_schur", "fe_dense_symeig", "fe_gnn_param_count",
             "fe_gnn_create", "fe_gnn_free", "fe_gnn_get_params", "fe_gnn_set_params",
             "fe_gnn_forward", "fe_gnn_backward", "fe_gnn_adam")
 
@@ -81,6 +81,7 @@ def lib():
             "fe_spmm": [P, P, P, i32, i32, P],
             "fe_gram": [P, i32, i64, P, i64, i32, i32, f64, P, P],
             "fe_block_update": [P, i64, i32, P, i32, i64, P, f64, f64, i32, P],
+            "fe_block_update_gram": [P, i64, i32, P, i32, i64, P, P, i32, P],
             "fe_krylov_schur": [P, i32, i32, i32, f64, ctypes.POINTER(KsOpts), P, P,
                                 ctypes.POINTER(KsReport)],
             "fe_dense_symeig": [i32, P, P, P],
@@ -225,6 +226,22 @@ def fe_gram(V, W, alpha: float = 1.0, C=None, stream=None):
     _check(lib().fe_gram(_dev_ptr(V), nblk, n * b, _dev_ptr(W), n, b, _dt_of(V), alpha,
                          _dev_ptr(C), _stream(stream)))
     return C
+
+
+def fe_block_update_gram(W, V, C, Cout=None, stream=None):
+    """W <- W - V C, then Cout = [V W]^T W ((k+b, b) FP64) in one pass over V."""
+    import torch
+    n, b = W.shape
+    nblk = V.shape[0]
+    if V.dim() != 3 or V.shape[1:] != (n, b) or V.dtype != W.dtype:
+        raise FeError(FE_EINVAL, "V must be (nblk, n, b) with W's dtype")
+    if C.shape != (nblk * b, b) or C.dtype != torch.float64:
+        raise FeError(FE_EINVAL, "C must be (k, b) float64")
+    if Cout is None:
+        Cout = torch.empty((nblk * b + b, b), dtype=torch.float64, device=W.device)
+    _check(lib().fe_block_update_gram(_dev_ptr(W), n, b, _dev_ptr(V), nblk, n * b, _dev_ptr(C),
+                                      _dev_ptr(Cout), _dt_of(W), _stream(stream)))
+    return Cout
 
 
 def fe_block_update(W, V, C, alpha: float = 1.0, beta: float = 1.0, stream=None):

@@ -138,14 +138,19 @@ def large(args):
          f"{x['gbs']:.0f} GB/s ({100 * x['frac']:.1f}% of 8 TB/s)")
     gc.collect()
     torch.cuda.empty_cache()
-    ref_row, ref = run_solve(F, A, "f64_reference", nev=nev, block=b, m=m, tol=1e-10,
-                             dtype=torch.float64, seed=2)
-    rows = [ref_row]
-    torch.cuda.empty_cache()
-    rows.append(run_solve(F, A, "f32_random_start", ref.evals, nev=nev, block=b, m=m,
-                          tol=1e-6, dtype=torch.float32, seed=1)[0])
-    torch.cuda.empty_cache()
-    if args.weights:
+    runs = set(args.runs.split(","))
+    rows, ref_evals = [], None
+    if "f64" in runs:
+        ref_row, ref = run_solve(F, A, "f64_reference", nev=nev, block=b, m=m, tol=1e-10,
+                                 dtype=torch.float64, seed=2)
+        rows.append(ref_row)
+        ref_evals = ref.evals
+        torch.cuda.empty_cache()
+    if "f32" in runs:
+        rows.append(run_solve(F, A, "f32_random_start", ref_evals, nev=nev, block=b, m=m,
+                              tol=1e-6, dtype=torch.float32, seed=1)[0])
+        torch.cuda.empty_cache()
+    if args.weights and ("learned" in runs or "learned32" in runs):
         net = F.Gnn(seed=0, compute="bf16")
         net.set_params(np.load(args.weights))
         torch.cuda.synchronize()
@@ -159,15 +164,20 @@ def large(args):
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - t0
         _log(f"[study] network inference {t_inf:.2f} s (fallback: {X is None})")
-        row, _ = run_solve(F, A, "learned_start_mixed", ref.evals, nev=nev, block=b, m=m,
-                           tol=1e-6, dtype=torch.float32, seed=1, start=X, mixed=True)
-        row["inference_s"] = t_inf
-        row["end_to_end_s"] = t_inf + row["seconds"]
-        row["fallback"] = X is None
-        rows.append(row)
+        for tag, mixed in (("learned", True), ("learned32", False)):
+            if tag not in runs:
+                continue
+            row, _ = run_solve(F, A, "learned_start_" + ("mixed" if mixed else "f32"), ref_evals,
+                               nev=nev, block=b, m=m, tol=1e-6, dtype=torch.float32, seed=1,
+                               start=X, mixed=mixed)
+            row["inference_s"] = t_inf
+            row["end_to_end_s"] = t_inf + row["seconds"]
+            row["fallback"] = X is None
+            rows.append(row)
         del X
         torch.cuda.empty_cache()
-        rows.append(run_solve(F, A, "random_start_mixed", ref.evals, nev=nev, block=b, m=m,
+    if "mixed" in runs:
+        rows.append(run_solve(F, A, "random_start_mixed", ref_evals, nev=nev, block=b, m=m,
                               tol=1e-6, dtype=torch.float32, seed=1, mixed=True)[0])
     out["solves"] = rows
     print(json.dumps(out), flush=True)
@@ -187,6 +197,8 @@ def main():
     q.add_argument("--m", type=int, default=48)
     q.add_argument("--weights", default=None)
     q.add_argument("--spmm-reps", type=int, default=10)
+    q.add_argument("--runs", default="f64,f32,learned,learned32,mixed",
+                   help="solves: f64 (reference), f32, learned (mixed storage), learned32, mixed")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)

@@ -114,3 +114,72 @@ def test_update_rejects_overlap(fe):
     with pytest.raises(fe.FeError) as e:
         fe.fe_block_update(V[1], V, C)
     assert e.value.status == fe.FE_EINVAL
+
+
+# ----------------------------------------------- fused update + Gram
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n,nblk,b", [(1, 1, 1), (1000, 3, 4), (4097, 12, 4), (4097, 8, 8),
+                                      (999, 2, 16), (130, 4, 16), (70001, 12, 4), (65, 5, 2)])
+def test_update_gram_small_int_bitwise(fe, dt, n, nblk, b):
+    """Integer inputs: W' = W - V C exactly (then rounded to the storage type),
+    and [V W']^T W' exactly, from the rounded W'."""
+    V = S.small_ints((nblk, n, b), seed=21, lo=-3, hi=3)
+    W = S.small_ints((n, b), seed=22, lo=-3, hi=3)
+    C = S.small_ints((nblk * b, b), seed=23, lo=-3, hi=3)
+    Wd = dev(W, DT[dt])
+    Cout = host(fe.fe_block_update_gram(Wd, dev(V, DT[dt]), dev(C, torch.float64)))
+    Vf = V.transpose(1, 0, 2).reshape(n, nblk * b)
+    Wn = O.block_update(W, Vf, C, alpha=-1.0, beta=1.0)
+    if dt == "bf16":
+        Wn = O.round_bf16(Wn)
+    assert np.array_equal(host(Wd), Wn)
+    assert np.array_equal(Cout, O.gram(np.hstack([Vf, Wn]), Wn))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n,nblk,b", [(100003, 12, 4), (30001, 6, 8), (4096, 3, 16), (777, 1, 1)])
+def test_update_gram_normal(fe, dt, n, nblk, b):
+    Vd = dev(S.normal((nblk, n, b), seed=24), DT[dt])
+    Wd = dev(S.normal((n, b), seed=25), DT[dt])
+    C = S.normal((nblk * b, b), seed=26)
+    V, W = host(Vd), host(Wd)
+    Vf = V.transpose(1, 0, 2).reshape(n, nblk * b)
+    want = O.block_update(W, Vf, C, alpha=-1.0, beta=1.0)
+    mag = np.abs(W) + np.abs(Vf) @ np.abs(C)
+    Cout = host(fe.fe_block_update_gram(Wd, Vd, dev(C, torch.float64)))
+    got = host(Wd)
+    assert np.all(np.abs(got - want) <= ULP[dt] * np.abs(want) + 1e-13 * mag + 1e-300)
+    X = np.hstack([Vf, got])  # the Gram is taken from the rounded result
+    bound = 1e-13 * (np.abs(X).T @ np.abs(got))
+    assert np.all(np.abs(Cout - O.gram(X, got)) <= bound)
+
+
+def test_update_gram_equals_separate_calls(fe):
+    n, nblk, b = 20000, 6, 8
+    Vd = dev(S.normal((nblk, n, b), seed=27), torch.float32)
+    W0 = dev(S.normal((n, b), seed=28), torch.float32)
+    C = dev(S.normal((nblk * b, b), seed=29), torch.float64)
+    W1, W2 = W0.clone(), W0.clone()
+    Cf = host(fe.fe_block_update_gram(W1, Vd, C))
+    fe.fe_block_update(W2, Vd, C, alpha=-1.0, beta=1.0)
+    Cs = host(fe.fe_gram(torch.cat([Vd, W2.unsqueeze(0)]), W2))
+    assert torch.equal(W1, W2)  # identical FP64 arithmetic per element, same rounding
+    assert np.allclose(Cf, Cs, rtol=1e-12, atol=1e-9)
+
+
+def test_update_gram_rejects(fe):
+    V = torch.zeros((3, 100, 4), dtype=torch.float32, device="cuda")
+    C = torch.zeros((12, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(fe.FeError) as e:
+        fe.fe_block_update_gram(V[1], V, C)
+    assert e.value.status == fe.FE_EINVAL
+    V3 = torch.zeros((2, 100, 3), dtype=torch.float32, device="cuda")
+    W3 = torch.zeros((100, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(fe.FeError) as e:
+        fe.fe_block_update_gram(W3, V3, torch.zeros((6, 3), dtype=torch.float64, device="cuda"))
+    assert e.value.status == fe.FE_EUNSUPPORTED
+    V17 = torch.zeros((17, 100, 4), dtype=torch.float32, device="cuda")  # k = 68 > 64
+    W4 = torch.zeros((100, 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(fe.FeError) as e:
+        fe.fe_block_update_gram(W4, V17, torch.zeros((68, 4), dtype=torch.float64, device="cuda"))
+    assert e.value.status == fe.FE_EUNSUPPORTED

@@ -1,0 +1,77 @@
+"""What the trained start block gains over the method without it.
+
+The committed weights (paper_1602_01421_amd/weights/gnn_start.npy, trained on
+generated graphs with seeds 1000..2999, validation 9000..9099) are run on
+held-out graphs of the same family (seeds from 3000): FP64 storage, nev 8,
+block 8, m 48, tol 1e-8, learned start vs the median of three random starts.
+Bars (set with margin under what the held-out evaluation measured, a median
+of 0.85 of the random products on Chung-Lu graphs): on the first 12 held-out
+Chung-Lu graphs with n <= 2^16 the learned start needs no more products than
+the random median on at least 9, and at most 0.95 of their total; every
+learned solve converges and passes the solver's own FP64 residual check.
+Plus the fallback: a network whose output is not finite or rank deficient
+yields no start block, and the solve then runs from a random start.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import fe_synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+def heldout_chung_lu(count=12, max_n=1 << 16):
+    out, seed = [], 3000
+    while len(out) < count:
+        rng = np.random.default_rng(seed)  # the recipe's first draws: family, then size
+        kind = "chung_lu" if rng.random() < 0.5 else "sbm"
+        n = 1 << int(rng.integers(14, 19))
+        if kind == "chung_lu" and n <= max_n:
+            out.append(seed)
+        seed += 1
+    return out
+
+
+def test_learned_start_needs_fewer_products(fe):
+    from paper_1602_01421_amd import learned as L
+    assert os.path.exists(L.DEFAULT_WEIGHTS), "trained weights are part of the package"
+    net = fe.Gnn(seed=0)
+    net.set_params(np.load(L.DEFAULT_WEIGHTS))
+    wins, tot_l, tot_r = 0, 0, 0
+    for seed in heldout_chung_lu():
+        A, z, desc = L.build_graph(seed)
+        assert desc.startswith("chung_lu")
+        rand = [L.solve(A, seed=100 + k) for k in range(3)]
+        X = L.learned_start(net, A, z, torch.float64)
+        assert X is not None, desc
+        r = L.solve(A, start=X, seed=1)
+        assert r.status == fe.FE_OK and r.resid.max() <= 1e-7, desc
+        assert all(q.status == fe.FE_OK for q in rand)
+        med = float(np.median([q.spmm_calls for q in rand]))
+        assert np.allclose(r.evals, rand[0].evals, rtol=1e-9, atol=1e-9), desc
+        wins += r.spmm_calls <= med
+        tot_l += r.spmm_calls
+        tot_r += med
+        print(f"{desc}: learned {r.spmm_calls} products, random median {med:.0f}")
+    assert wins >= 9, wins
+    assert tot_l <= 0.95 * tot_r, (tot_l, tot_r)
+
+
+def test_fallback_to_random_start(fe):
+    from paper_1602_01421_amd import learned as L
+    A, z, desc = L.build_graph(3001, max_log2n=14)
+    bad = fe.Gnn(seed=0)
+    p = bad.get_params()
+    p[:] = np.nan
+    bad.set_params(p)
+    assert L.learned_start(bad, A, z, torch.float64) is None  # non-finite output
+    flat = fe.Gnn(seed=0)
+    p = flat.get_params()
+    p[:] = 0.0  # zero weights and biases: X = 0, a singular Gram
+    flat.set_params(p)
+    assert L.learned_start(flat, A, z, torch.float64) is None
+    r = L.solve(A, start=None, seed=5)
+    assert r.status == fe.FE_OK
