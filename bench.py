@@ -112,12 +112,13 @@ def cpu_baseline(n, s, d, nnz, budget_s=25.0):
                       f"{t:.1f} s (oracle CSR build {t_csr:.1f} s not timed)"}
 
 
-def learned_vs_random(P, A, stream, weights, tol, m=48, seeds=3):
+def learned_vs_random(P, A, stream, weights, tol, block, m, seeds=3):
     """Time to 8 eigenpairs from the learned start block vs random starts.
 
-    Block 8 (the network's 8 output columns), FP32 storage.  The learned time
-    is end to end: drawing the network's N(0,1) inputs on the GPU, inference,
-    the fallback check and the solve.
+    The same solve as the timed steps (FP32 storage, nev 8, `block`, `m`); for
+    block < 8 the network's 8 outputs are folded to `block` columns.  The
+    learned time is end to end: drawing the network's N(0,1) inputs on the
+    GPU, inference, the fallback check and the solve.
     """
     import numpy as np
     import torch
@@ -126,8 +127,8 @@ def learned_vs_random(P, A, stream, weights, tol, m=48, seeds=3):
     net.set_params(np.load(weights))
 
     def solve(start=None, seed=1):
-        return P.fe_krylov_schur(A, 8, 8, m, tol, dtype=torch.float32, start=start, seed=seed,
-                                 stream=stream, want_vectors=False)
+        return P.fe_krylov_schur(A, 8, block, m, tol, dtype=torch.float32, start=start,
+                                 seed=seed, stream=stream, want_vectors=False)
 
     solve(seed=99)  # warm-up at this block width
     rand = []
@@ -144,7 +145,7 @@ def learned_vs_random(P, A, stream, weights, tol, m=48, seeds=3):
         g = torch.Generator(device="cuda")
         g.manual_seed(1 + k)
         z = torch.randn((A.n, 15), generator=g, device="cuda", dtype=torch.float32)
-        X = learned_start(net, A, z, torch.float32)
+        X = learned_start(net, A, z, torch.float32, block=block)
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - t0
         r = solve(start=X, seed=1 + k)
@@ -153,7 +154,7 @@ def learned_vs_random(P, A, stream, weights, tol, m=48, seeds=3):
         del z, X
     net.close()
     med = lambda xs: float(np.median(xs))  # noqa: E731
-    res = {"block": 8, "m": m, "tol": tol, "dtype": "f32", "seeds": seeds,
+    res = {"block": block, "m": m, "tol": tol, "dtype": "f32", "seeds": seeds,
            "random_s": med([x[0] for x in rand]), "random_spmm": med([x[1] for x in rand]),
            "learned_s": med([x[0] for x in learned]),
            "learned_spmm": med([x[1] for x in learned]),
@@ -162,7 +163,7 @@ def learned_vs_random(P, A, stream, weights, tol, m=48, seeds=3):
            "all_converged": all(x[2] == 0 for x in rand + learned)}
     res["time_ratio"] = res["learned_s"] / res["random_s"]
     res["spmm_ratio"] = res["learned_spmm"] / res["random_spmm"]
-    log(f"time to 8 eigs (b=8, m={m}, FP32): random {res['random_s']:.3f} s / "
+    log(f"time to 8 eigs (b={block}, m={m}, FP32): random {res['random_s']:.3f} s / "
         f"{res['random_spmm']:.0f} products, learned {res['learned_s']:.3f} s / "
         f"{res['learned_spmm']:.0f} products (inference {res['inference_s']*1e3:.1f} ms)")
     return res
@@ -287,7 +288,7 @@ def main():
         "build_s": t_build,
     }
     if args.weights and os.path.exists(args.weights):
-        out["learned_vs_random"] = learned_vs_random(P, A, stream, args.weights, tol)
+        out["learned_vs_random"] = learned_vs_random(P, A, stream, args.weights, tol, block, m)
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(n, s, d, A.nnz)

@@ -211,8 +211,10 @@ typedef struct {
  * Block Krylov-Schur for the nev largest-magnitude eigenpairs of the
  * symmetric pattern matrix A (the paper's selected solver, following its
  * generic eigen-iteration with the block extension).  block = b vectors per
- * step, m = subspace size (m % block == 0, 1 <= nev <= m - block, m <= 128,
- * block <= 16, m + block <= n), tol > 0: pair i is converged when its
+ * step, m = subspace size (m % block == 0, 1 <= nev <= m - block, m <= 128
+ * and m <= 64 with FP64 storage, block in {1,2,4,8,16}, m + block <= n; the
+ * restart keeps p = m - block * max(1, (m - nev) / (2 block)) vectors, p <= 64
+ * and m * p <= 8192), tol > 0: pair i is converged when its
  * Krylov-Schur residual estimate is <= tol * max(eps^(2/3), |theta_i|), eps
  * the FP64 unit roundoff.
  * Final check (FP64 whatever the storage dtype): the Ritz vectors X = V Y are
@@ -271,9 +273,15 @@ void fe_gnn_free(fe_gnn *g);
 fe_status fe_gnn_get_params(const fe_gnn *g, float *host);
 fe_status fe_gnn_set_params(fe_gnn *g, const float *host);
 
-/* X (device n x 8 FP32) = network output for graph A with random features z
-   (device n x 15 FP32).  Synchronises the stream.  Errors: FE_EINVAL, FE_ENOMEM, FE_EDEVICE. */
-fe_status fe_gnn_forward(fe_gnn *g, const fe_csr *A, const float *z, float *X, void *hip_stream);
+/* Start block X (device n x block FP32, original vertex order) from the
+   network's 8 outputs for graph A with random features z (device n x 15
+   FP32): block = 8 returns the outputs; block = 1, 2 or 4 folds them, column
+   c summing the outputs j = c (mod block), so the block still carries every
+   output direction for a solver that starts from fewer columns.
+   Synchronises the stream.  Errors: FE_EINVAL (NULL, block not in
+   {1,2,4,8}), FE_ENOMEM, FE_EDEVICE. */
+fe_status fe_gnn_forward(fe_gnn *g, const fe_csr *A, const float *z, float *X, int32_t block,
+                         void *hip_stream);
 
 /* Forward, loss against V (device n x 8 FP32, orthonormal columns) and
    backward; the gradients are kept in g (and copied to grads_host, 19,136

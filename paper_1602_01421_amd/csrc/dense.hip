@@ -411,12 +411,15 @@ fe_status update_t(void* W, int64_t n, int32_t b, const void* V, int32_t nblk, i
 }
 
 // ------------------------------------------------------- rotate / combine
-// Out row r = (V row r) * Y, Y is m x p (FP64, LDS).  All of a row's inputs
-// are read before any of its outputs is written, so the in-place form
-// (Out = the first p/b blocks of V) is safe row by row.
-constexpr int kRotMax = 64;
+// Out row r = (V row r) * Y, Y is m x p (FP64, LDS).  All of a row's m inputs
+// are read into registers before any of its outputs is written, so the
+// in-place form (Out = the first p/b blocks of V) is safe row by row.  MAXM
+// bounds m: 64, or 128 for 2- and 4-byte storage (128 FP64 inputs would not
+// fit the register file).
+constexpr int kRotMax = 64;    // outputs per row (p, or c_out)
+constexpr int kRotRows = 128;  // largest m
 
-template <typename T, typename TO, int B>
+template <typename T, typename TO, int B, int MAXM>
 __global__ __launch_bounds__(256) void rotate_kernel(TO* Out, int32_t out_mode,
                                                      int32_t c_out, int64_t n, const T* V,
                                                      int32_t nblk, int64_t stride,
@@ -429,9 +432,9 @@ __global__ __launch_bounds__(256) void rotate_kernel(TO* Out, int32_t out_mode,
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   constexpr int VEC = (B * sizeof(T) >= 16) ? 16 / sizeof(T) : B;
-  constexpr int NB = kRotMax / B;
+  constexpr int NB = MAXM / B;
   // the row's m inputs, read once (all reads precede any write of the row)
-  A v[kRotMax];
+  A v[MAXM];
 #pragma unroll
   for (int jb = 0; jb < NB; ++jb) {
     if (jb < nblk) {
@@ -446,13 +449,13 @@ __global__ __launch_bounds__(256) void rotate_kernel(TO* Out, int32_t out_mode,
   if constexpr (sizeof(TO) == sizeof(T)) {
     if (out_mode == 0) {  // back into the first p/B blocks of V
 #pragma unroll
-      for (int ob = 0; ob < NB; ++ob) {
+      for (int ob = 0; ob < kRotMax / B; ++ob) {
         if (ob * B < p) {
           double acc[B];
 #pragma unroll
           for (int q = 0; q < B; ++q) acc[q] = 0.0;
 #pragma unroll
-          for (int t = 0; t < kRotMax; ++t) {
+          for (int t = 0; t < MAXM; ++t) {
             if (t < m) {
               const double* yr = Ys + t * p + ob * B;
 #pragma unroll
@@ -471,7 +474,7 @@ __global__ __launch_bounds__(256) void rotate_kernel(TO* Out, int32_t out_mode,
   for (int o = 0; o < c_out; ++o) {
     double acc = 0.0;
 #pragma unroll
-    for (int t = 0; t < kRotMax; ++t)
+    for (int t = 0; t < MAXM; ++t)
       if (t < m) acc = fma((double)v[t], Ys[t * p + o], acc);
     Out[r * c_out + o] = to_storage<TO, double>(acc);
   }
@@ -482,20 +485,33 @@ fe_status rotate_t(void* Out, int32_t out_mode, int32_t c_out, int64_t n, int32_
                    const void* V, int32_t nblk, int64_t stride, const double* Y, int32_t p,
                    hipStream_t s) {
   const int64_t g = (n + 255) / 256;
-  const size_t lds = (size_t)nblk * b * p * sizeof(double);
-  if (p > kRotMax || lds > 64 * 1024)
-    return fail(FE_EUNSUPPORTED, "rotate: p=%d (max %d) or m*p too large", p, kRotMax);
+  const int m = nblk * b;
+  const size_t lds = (size_t)m * p * sizeof(double);
+  constexpr int kMaxRows = sizeof(T) == 8 ? kRotMax : kRotRows;
+  if (p > kRotMax || m > kMaxRows || lds > 64 * 1024)
+    return fail(FE_EUNSUPPORTED, "rotate: m=%d (max %d), p=%d (max %d) or m*p too large", m,
+                kMaxRows, p, kRotMax);
   TO* O = static_cast<TO*>(Out);
   const T* Vp = static_cast<const T*>(V);
-#define FE_ROT(BB)                                                                                \
+#define FE_ROT(BB, MM)                                                                            \
   case BB:                                                                                        \
-    hipLaunchKernelGGL((rotate_kernel<T, TO, BB>), dim3((uint32_t)g), dim3(256), lds, s, O, out_mode, \
-                       c_out, n, Vp, nblk, stride, Y, p);                                        \
+    hipLaunchKernelGGL((rotate_kernel<T, TO, BB, MM>), dim3((uint32_t)g), dim3(256), lds, s, O,  \
+                       out_mode, c_out, n, Vp, nblk, stride, Y, p);                              \
     break;
-  switch (b) {
-    FE_ROT(1) FE_ROT(2) FE_ROT(4) FE_ROT(8) FE_ROT(16)
-    default:
-      return fail(FE_EUNSUPPORTED, "rotate: block %d not in {1,2,4,8,16}", b);
+  if (m <= kRotMax) {
+    switch (b) {
+      FE_ROT(1, kRotMax) FE_ROT(2, kRotMax) FE_ROT(4, kRotMax) FE_ROT(8, kRotMax)
+      FE_ROT(16, kRotMax)
+      default:
+        return fail(FE_EUNSUPPORTED, "rotate: block %d not in {1,2,4,8,16}", b);
+    }
+  } else if constexpr (sizeof(T) < 8) {
+    switch (b) {
+      FE_ROT(1, kRotRows) FE_ROT(2, kRotRows) FE_ROT(4, kRotRows) FE_ROT(8, kRotRows)
+      FE_ROT(16, kRotRows)
+      default:
+        return fail(FE_EUNSUPPORTED, "rotate: block %d not in {1,2,4,8,16}", b);
+    }
   }
 #undef FE_ROT
   FE_HIP(hipGetLastError());

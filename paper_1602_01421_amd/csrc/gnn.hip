@@ -87,9 +87,12 @@ __global__ void combine_kernel(float* __restrict__ out, const float* __restrict_
 }
 
 // X = H3 P (row r of the internal order is written to row perm[r] of Xout too)
+// X = H3 P (internal order, kept for the backward pass) and/or Xout in the
+// original vertex order with wout columns: column c of Xout sums the outputs
+// j = c (mod wout) in ascending j (wout = 8: the outputs themselves).
 __global__ void out_fwd_kernel(const float* __restrict__ H3, const float* __restrict__ P,
                                int64_t n, float* __restrict__ X, const int32_t* __restrict__ perm,
-                               float* __restrict__ Xout) {
+                               float* __restrict__ Xout, int32_t wout) {
   __shared__ float Ps[HID * NOUT];
   for (int i = threadIdx.x; i < HID * NOUT; i += blockDim.x) Ps[i] = P[i];
   __syncthreads();
@@ -104,10 +107,16 @@ __global__ void out_fwd_kernel(const float* __restrict__ H3, const float* __rest
     for (int j = 0; j < NOUT; ++j) acc[j] = fmaf(h, Ps[k * NOUT + j], acc[j]);
   }
   const int64_t o = perm ? (int64_t)perm[r] : r;
+  if (X) {
 #pragma unroll
-  for (int j = 0; j < NOUT; ++j) {
-    if (X) X[r * NOUT + j] = acc[j];
-    if (Xout) Xout[o * NOUT + j] = acc[j];
+    for (int j = 0; j < NOUT; ++j) X[r * NOUT + j] = acc[j];
+  }
+  if (Xout) {
+    for (int c = 0; c < wout; ++c) {
+      float sum = acc[c];
+      for (int j = c + wout; j < NOUT; j += wout) sum += acc[j];
+      Xout[o * wout + c] = sum;
+    }
   }
 }
 
@@ -554,7 +563,7 @@ struct Fwd {
 // two buffers, while Hs and T each need one (Hs[l] is consumed by the product
 // that makes T[l] before layer l writes Hs[l+1]; T[l] is read only by layer l).
 fe_status forward(const Gnn& g, const Csr& A, const float* z, Ws& ws, Fwd& f, float* Xorig,
-                  bool keep = true) {
+                  bool keep = true, int32_t wout = NOUT) {
   const int64_t n = A.n;
   const Offsets o = offsets();
   hipStream_t s = ws.s;
@@ -603,7 +612,7 @@ fe_status forward(const Gnn& g, const Csr& A, const float* z, Ws& ws, Fwd& f, fl
     FE_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(out_fwd_kernel, grid1(n), dim3(256), 0, s, f.H[NLAYER], g.params + o.P, n,
-                     f.X, perm, Xorig);
+                     keep ? f.X : nullptr, perm, Xorig, wout);
   FE_HIP(hipGetLastError());
   return FE_OK;
 }
@@ -707,14 +716,17 @@ fe_status fe_gnn_set_params(fe_gnn* g, const float* host) {
   return FE_OK;
 }
 
-fe_status fe_gnn_forward(fe_gnn* g, const fe_csr* A, const float* z, float* X, void* stream) {
+fe_status fe_gnn_forward(fe_gnn* g, const fe_csr* A, const float* z, float* X, int32_t block,
+                         void* stream) {
   if (!g || !A || !z || !X) return fail(FE_EINVAL, "fe_gnn_forward: NULL argument");
+  if (block != 1 && block != 2 && block != 4 && block != 8)
+    return fail(FE_EINVAL, "fe_gnn_forward: block must be 1, 2, 4 or 8");
   hipStream_t s = (hipStream_t)stream;
   {
     Ws ws(s, g);
     FE_TRY(ws.grow());
     Fwd f;
-    FE_TRY(forward(*g, *A, z, ws, f, X, false));
+    FE_TRY(forward(*g, *A, z, ws, f, X, false, block));
   }
   FE_HIP(hipStreamSynchronize(s));
   return FE_OK;

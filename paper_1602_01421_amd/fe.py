@@ -88,7 +88,7 @@ def lib():
             "fe_gnn_create": [ctypes.c_uint64, i32, ctypes.POINTER(P)],
             "fe_gnn_get_params": [P, P],
             "fe_gnn_set_params": [P, P],
-            "fe_gnn_forward": [P, P, P, P, P],
+            "fe_gnn_forward": [P, P, P, P, i32, P],
             "fe_gnn_backward": [P, P, P, P, ctypes.POINTER(ctypes.c_double), P, P],
             "fe_gnn_adam": [P, f64, f64, P],
         }
@@ -382,12 +382,15 @@ class Gnn:
         assert flat.shape == (self.count,)
         _check(lib().fe_gnn_set_params(self._h, _np_ptr(flat)))
 
-    def forward(self, A: Csr, z, X=None, stream=None):
-        """X (n x 8, original vertex order) for random features z (n x 15, FP32 device)."""
+    def forward(self, A: Csr, z, X=None, block: int = 8, stream=None):
+        """Start block X (n x block, original vertex order) for random features z
+        (n x 15, FP32 device); block < 8 folds the 8 outputs (column c sums
+        outputs c, c + block, ...)."""
         import torch
         if X is None:
-            X = torch.empty((A.n, 8), dtype=torch.float32, device="cuda")
-        _check(lib().fe_gnn_forward(self._h, A.handle, _dev_ptr(z), _dev_ptr(X), _stream(stream)))
+            X = torch.empty((A.n, block), dtype=torch.float32, device="cuda")
+        _check(lib().fe_gnn_forward(self._h, A.handle, _dev_ptr(z), _dev_ptr(X), block,
+                                    _stream(stream)))
         return X
 
     def backward(self, A: Csr, z, V, want_grads: bool = False, stream=None):

@@ -10,8 +10,12 @@ of a solve started from the network's block against random starts.
 Fallback: the learned solve reverts to a random start when the network's
 output is not finite or its Gram matrix is numerically singular.
 
-    python -m paper_1602_01421_amd.learned train --graphs 400 --epochs 10 --out W.npy
-    python -m paper_1602_01421_amd.learned eval --weights W.npy --heldout 40
+    python -m paper_1602_01421_amd.learned train --out W.npy      # the committed weights
+    python -m paper_1602_01421_amd.learned eval --weights W.npy --heldout 200
+
+Training runs the forward pass in FP32 (BF16-mode training diverged: the
+subspace-loss gradient magnifies BF16 rounding); inference uses the BF16
+forward with the trained FP32 weights.
 """
 from __future__ import annotations
 
@@ -53,15 +57,16 @@ def label(A, seed: int = 1):
     return r.evecs.float().contiguous(), r
 
 
-def learned_start(net, A, z, dtype):
-    """Start block from the network, or None when it must fall back to random.
+def learned_start(net, A, z, dtype, block: int = 8):
+    """Start block (n x block) from the network, or None when it must fall back
+    to random.  block < 8 folds the network's 8 outputs (fe_gnn_forward).
 
     One FP64 Gram of the output decides: a non-finite entry, or a smallest
     eigenvalue below 1e-10 of the largest (numerically dependent columns),
     means fallback.
     """
     from . import fe as F
-    X = net.forward(A, z)
+    X = net.forward(A, z, block=block)
     G = F.fe_gram(X.unsqueeze(0), X).cpu().numpy()
     if not np.all(np.isfinite(G)):
         return None
@@ -215,17 +220,18 @@ def main():
     t = sub.add_parser("train")
     t.add_argument("--graphs", type=int, default=2000)
     t.add_argument("--first-seed", type=int, default=1000)
-    t.add_argument("--epochs", type=int, default=20)
-    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--epochs", type=int, default=200)
+    t.add_argument("--lr", type=float, default=5e-4)
     t.add_argument("--init-seed", type=int, default=0)
     t.add_argument("--max-log2n", type=int, default=18)
     t.add_argument("--out", default=DEFAULT_WEIGHTS)
-    t.add_argument("--compute", default="bf16", choices=["bf16", "f32"])
+    t.add_argument("--compute", default="f32", choices=["bf16", "f32"],
+                   help="training forward precision (inference runs BF16 either way)")
     t.add_argument("--clip", type=float, default=1.0, help="global gradient-norm clip (0: off)")
     t.add_argument("--val", type=int, default=100, help="validation graphs")
     t.add_argument("--val-seed", type=int, default=9000)
-    t.add_argument("--label-budget", type=float, default=1e9, help="seconds")
-    t.add_argument("--time-budget", type=float, default=1e9, help="seconds, whole run")
+    t.add_argument("--label-budget", type=float, default=300.0, help="seconds")
+    t.add_argument("--time-budget", type=float, default=760.0, help="seconds, whole run")
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=DEFAULT_WEIGHTS)
     e.add_argument("--heldout", type=int, default=200)

@@ -83,11 +83,15 @@ def time_spmm(F, A, b, dtype, reps=10):
             "frac": algo / t / 1e9 / HBM_PEAK_GBS}
 
 
+VERBOSE = False
+
+
 def run_solve(F, A, label, ref=None, **kw):
     import torch
     torch.cuda.synchronize()
+    _log(f"[study] {label}: solving")
     t0 = time.perf_counter()
-    r = F.fe_krylov_schur(A, want_vectors=False, **kw)
+    r = F.fe_krylov_schur(A, want_vectors=False, verbose=VERBOSE, **kw)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     row = {"run": label, "status": int(r.status), "seconds": t, "restarts": r.restarts,
@@ -126,31 +130,41 @@ def precision(args):
 
 def large(args):
     from . import fe as F
-    from .learned import learned_start
     import torch
     A, info = build_rmat(F, args.scale)
-    nev, b, m = 8, args.block, args.m
     out = {"study": "large", "graph": f"rmat{args.scale}", "n": A.n, "nnz": A.nnz,
-           "max_deg": A.max_deg, "nev": nev, "block": b, "m": m, **info}
-    out["spmm"] = [time_spmm(F, A, b, torch.float32, reps=args.spmm_reps)]
-    x = out["spmm"][0]
-    _log(f"[study] product b={b} FP32: {x['ms']:.2f} ms, {x['gedge_col_s']:.0f} GEdge*col/s, "
-         f"{x['gbs']:.0f} GB/s ({100 * x['frac']:.1f}% of 8 TB/s)")
+           "max_deg": A.max_deg, **info, "spmm": [], "configs": []}
+    for b in sorted({int(c.split("x")[0]) for c in args.configs.split(",")}):
+        x = time_spmm(F, A, b, torch.float32, reps=args.spmm_reps)
+        out["spmm"].append(x)
+        _log(f"[study] product b={b} FP32: {x['ms']:.2f} ms, {x['gedge_col_s']:.0f} GEdge*col/s, "
+             f"{x['gbs']:.0f} GB/s ({100 * x['frac']:.1f}% of 8 TB/s)")
     gc.collect()
     torch.cuda.empty_cache()
+    for c in args.configs.split(","):
+        b, m = (int(v) for v in c.split("x"))
+        out["configs"].append(large_config(F, A, args, 8, b, m))
+    print(json.dumps(out), flush=True)
+
+
+def large_config(F, A, args, nev, b, m):
+    from .learned import learned_start
+    import torch
+    _log(f"[study] configuration nev {nev}, block {b}, m {m}")
+    mr = args.max_restarts
     runs = set(args.runs.split(","))
     rows, ref_evals = [], None
     if "f64" in runs:
         ref_row, ref = run_solve(F, A, "f64_reference", nev=nev, block=b, m=m, tol=1e-10,
-                                 dtype=torch.float64, seed=2)
+                                 dtype=torch.float64, seed=2, max_restarts=mr)
         rows.append(ref_row)
         ref_evals = ref.evals
         torch.cuda.empty_cache()
     if "f32" in runs:
         rows.append(run_solve(F, A, "f32_random_start", ref_evals, nev=nev, block=b, m=m,
-                              tol=1e-6, dtype=torch.float32, seed=1)[0])
+                              tol=1e-6, dtype=torch.float32, seed=1, max_restarts=mr)[0])
         torch.cuda.empty_cache()
-    if args.weights and ("learned" in runs or "learned32" in runs):
+    if args.weights and b in (1, 2, 4, 8) and ("learned" in runs or "learned32" in runs):
         net = F.Gnn(seed=0, compute="bf16")
         net.set_params(np.load(args.weights))
         torch.cuda.synchronize()
@@ -158,7 +172,7 @@ def large(args):
         g = torch.Generator(device="cuda")
         g.manual_seed(args.scale)
         z = torch.randn((A.n, 15), generator=g, device="cuda", dtype=torch.float32)
-        X = learned_start(net, A, z, torch.float32)
+        X = learned_start(net, A, z, torch.float32, block=b)
         del z
         net.close()  # releases the inference workspace (4 x n x 64 floats)
         torch.cuda.synchronize()
@@ -169,7 +183,7 @@ def large(args):
                 continue
             row, _ = run_solve(F, A, "learned_start_" + ("mixed" if mixed else "f32"), ref_evals,
                                nev=nev, block=b, m=m, tol=1e-6, dtype=torch.float32, seed=1,
-                               start=X, mixed=mixed)
+                               start=X, mixed=mixed, max_restarts=mr)
             row["inference_s"] = t_inf
             row["end_to_end_s"] = t_inf + row["seconds"]
             row["fallback"] = X is None
@@ -178,9 +192,9 @@ def large(args):
         torch.cuda.empty_cache()
     if "mixed" in runs:
         rows.append(run_solve(F, A, "random_start_mixed", ref_evals, nev=nev, block=b, m=m,
-                              tol=1e-6, dtype=torch.float32, seed=1, mixed=True)[0])
-    out["solves"] = rows
-    print(json.dumps(out), flush=True)
+                              tol=1e-6, dtype=torch.float32, seed=1, mixed=True,
+                              max_restarts=mr)[0])
+    return {"nev": nev, "block": b, "m": m, "max_restarts": mr, "solves": rows}
 
 
 def main():
@@ -193,13 +207,19 @@ def main():
     p.add_argument("--bf16-restarts", type=int, default=200)
     q = sub.add_parser("large")
     q.add_argument("--scale", type=int, default=27)
-    q.add_argument("--block", type=int, default=8)
-    q.add_argument("--m", type=int, default=48)
+    q.add_argument("--configs", default="8x48",
+                   help="comma list of BLOCKxM solve shapes, all nev 8 (e.g. 8x48,4x64)")
+    q.add_argument("--max-restarts", type=int, default=500)
     q.add_argument("--weights", default=None)
     q.add_argument("--spmm-reps", type=int, default=10)
     q.add_argument("--runs", default="f64,f32,learned,learned32,mixed",
                    help="solves: f64 (reference), f32, learned (mixed storage), learned32, mixed")
+    for sp in (p, q):
+        sp.add_argument("--verbose", action="store_true",
+                        help="one line per restart from the solver (stderr)")
     args = ap.parse_args()
+    global VERBOSE
+    VERBOSE = args.verbose
     import torch
     torch.cuda.set_device(0)
     {"precision": precision, "large": large}[args.cmd](args)

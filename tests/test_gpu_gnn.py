@@ -124,3 +124,20 @@ def test_training_reduces_loss(fe):
         net.adam(3e-3)
     l1, _ = net.backward(A, zt, Vt)
     assert l1 < l0 - 0.05, (l0, l1)
+
+
+@pytest.mark.parametrize("block", [1, 2, 4])
+def test_forward_folds_outputs_to_block(fe, block):
+    """block < 8: column c is the sum of outputs c, c + block, ... (ascending)."""
+    A, rp, ci, z, V = case(fe, n=3000, seed=14, relabel=True)
+    net = fe.Gnn(seed=2)
+    zt = torch.tensor(z, dtype=torch.float32, device="cuda")
+    X8 = net.forward(A, zt)
+    Xb = net.forward(A, zt, block=block)
+    assert Xb.shape == (A.n, block)
+    want = X8[:, 0:block].clone()
+    for j in range(block, 8, block):
+        want += X8[:, j:j + block]
+    assert torch.equal(Xb, want)
+    with pytest.raises(fe.FeError):
+        net.forward(A, zt, block=3)

@@ -167,3 +167,28 @@ def test_rmat22_full_size_fp32(fe):
     # up to about 2^-24 * ||A|| (||A|| = |lambda_1|) to each residual
     rounding = 2.0 ** -23 * np.abs(r64.evals).max()
     assert np.all(res <= 1e-6 * np.abs(r32.evals) + rounding)
+
+
+@pytest.mark.parametrize("m", [96, 112])
+def test_subspace_beyond_64_fp32(fe, m):
+    """m > 64 (the restart reads all m basis columns of each row; p = 56, 64):
+    FP32 storage against the FP64 oracle run with the same shape."""
+    g = S.rmat_edges(14, seed=14)
+    A, rp, ci = setup(fe, g)
+    X0 = S.normal((A.n, 8), seed=3)
+    ref = oracle_ks(rp, ci, A.n, 8, 8, m, 1e-12, X0)
+    r = fe.fe_krylov_schur(A, 8, 8, m, 1e-6, dtype=torch.float32,
+                           start=torch.tensor(X0, dtype=torch.float32, device="cuda"))
+    assert r.status == fe.FE_OK
+    assert np.all(np.abs(r.evals - ref.evals) <= 1e-8 * np.abs(ref.evals))
+    assert r.resid.max() <= 1e-6
+    check_vectors(rp, ci, r)
+
+
+def test_subspace_limits(fe):
+    g = S.rmat_edges(12, seed=1)
+    A, rp, ci = setup(fe, g)
+    for args, dt in [((8, 8, 96), torch.float64), ((8, 8, 128), torch.float32)]:
+        with pytest.raises(fe.FeError) as e:
+            fe.fe_krylov_schur(A, *args, 1e-8, dtype=dt)
+        assert e.value.status == fe.FE_EUNSUPPORTED
