@@ -211,8 +211,8 @@ typedef struct {
  * Block Krylov-Schur for the nev largest-magnitude eigenpairs of the
  * symmetric pattern matrix A (the paper's selected solver, following its
  * generic eigen-iteration with the block extension).  block = b vectors per
- * step, m = subspace size (m % block == 0, 1 <= nev <= m - block, m <= 128
- * and m <= 64 with FP64 storage, block in {1,2,4,8,16}, m + block <= n; the
+ * step, m = subspace size (m % block == 0, 1 <= nev <= m - block, m <= 128,
+ * block in {1,2,4,8,16}, m + block <= n; the
  * restart keeps p = m - block * max(1, (m - nev) / (2 block)) vectors, p <= 64
  * and m * p <= 8192), tol > 0: pair i is converged when its
  * Krylov-Schur residual estimate is <= tol * max(eps^(2/3), |theta_i|), eps

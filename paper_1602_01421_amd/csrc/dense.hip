@@ -411,72 +411,68 @@ fe_status update_t(void* W, int64_t n, int32_t b, const void* V, int32_t nblk, i
 }
 
 // ------------------------------------------------------- rotate / combine
-// Out row r = (V row r) * Y, Y is m x p (FP64, LDS).  All of a row's m inputs
-// are read into registers before any of its outputs is written, so the
-// in-place form (Out = the first p/b blocks of V) is safe row by row.  MAXM
-// bounds m: 64, or 128 for 2- and 4-byte storage (128 FP64 inputs would not
-// fit the register file).
-constexpr int kRotMax = 64;    // outputs per row (p, or c_out)
+// Out = V Y for V (n x m, m/B packed blocks) and Y (m x p, FP64): the restart
+// V[:, :p] <- V Y in place, or the packed FP64 Ritz vectors.  A dense
+// tall-and-skinny contraction, so it runs on v_mfma_f64_16x16x4f64 (lane
+// layouts measured on gfx950: A lane i + 16k, B lane j + 16k, D lane
+// j + 16 (i mod 4), register i / 4): a wavefront owns 16 rows, takes the m
+// columns four at a time (one V value per lane per step, Y from LDS, padded
+// to whole 16-column tiles with zeros) and stores only after the last step,
+// so every input of its rows is read before any output of them is written and
+// the in-place form is safe.  FP64 arithmetic for every storage type.
+constexpr int kRotMax = 64;    // p (or c_out): at most four 16-column tiles
 constexpr int kRotRows = 128;  // largest m
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <typename T, typename TO, int B, int MAXM>
-__global__ __launch_bounds__(256) void rotate_kernel(TO* Out, int32_t out_mode,
+template <typename T, typename TO, int B>
+__global__ __launch_bounds__(256) void rotate_kernel(TO* Out, int32_t out_mode,  // may alias V
                                                      int32_t c_out, int64_t n, const T* V,
-                                                     int32_t nblk, int64_t stride,
-                                                     const double* __restrict__ Y, int32_t p) {
-  using A = typename Acc<T>::type;
-  extern __shared__ double Ys[];
+                                                     int32_t nblk,
+                                                     int64_t stride, const double* __restrict__ Y,
+                                                     int32_t p, int32_t p16) {
+  extern __shared__ double Ys[];  // m x p16
   const int m = nblk * B;
-  for (int i = threadIdx.x; i < m * p; i += blockDim.x) Ys[i] = Y[i];
-  __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  constexpr int VEC = (B * sizeof(T) >= 16) ? 16 / sizeof(T) : B;
-  constexpr int NB = MAXM / B;
-  // the row's m inputs, read once (all reads precede any write of the row)
-  A v[MAXM];
-#pragma unroll
-  for (int jb = 0; jb < NB; ++jb) {
-    if (jb < nblk) {
-      const T* vp = V + jb * stride + r * B;
-#pragma unroll
-      for (int c0 = 0; c0 < B; c0 += VEC) load_vec<T, VEC>(vp + c0, v + jb * B + c0);
-    } else {
-#pragma unroll
-      for (int c = 0; c < B; ++c) v[jb * B + c] = 0;
-    }
+  for (int i = threadIdx.x; i < m * p16; i += blockDim.x) {
+    const int t = i / p16, c = i - t * p16;
+    Ys[i] = c < p ? Y[t * p + c] : 0.0;
   }
-  if constexpr (sizeof(TO) == sizeof(T)) {
-    if (out_mode == 0) {  // back into the first p/B blocks of V
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ntile = p16 / 16;
+  const int64_t ngroups = (n + 15) / 16;
+  for (int64_t g = (int64_t)blockIdx.x * 4 + wave; g < ngroups; g += (int64_t)gridDim.x * 4) {
+    const int64_t r0 = g * 16;
+    const int64_t ra = min(r0 + li, n - 1);  // this lane's A row (clamped; not stored)
+    f64x4 acc[kRotMax / 16];
 #pragma unroll
-      for (int ob = 0; ob < kRotMax / B; ++ob) {
-        if (ob * B < p) {
-          double acc[B];
+    for (int t = 0; t < kRotMax / 16; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int kb = 0; kb < m; kb += 4) {
+      const int col = kb + lk;
+      const double a = load_f64(V + (int64_t)(col / B) * stride + ra * B + (col % B));
+      const double* yr = Ys + col * p16 + li;
 #pragma unroll
-          for (int q = 0; q < B; ++q) acc[q] = 0.0;
+      for (int t = 0; t < kRotMax / 16; ++t)
+        if (t < ntile) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, yr[16 * t], acc[t], 0, 0, 0);
+    }
 #pragma unroll
-          for (int t = 0; t < MAXM; ++t) {
-            if (t < m) {
-              const double* yr = Ys + t * p + ob * B;
+    for (int t = 0; t < kRotMax / 16; ++t) {
+      if (t < ntile) {
+        const int c = 16 * t + li;
 #pragma unroll
-              for (int q = 0; q < B; ++q) acc[q] = fma((double)v[t], yr[q], acc[q]);
+        for (int reg = 0; reg < 4; ++reg) {
+          const int64_t row = r0 + 4 * reg + lk;
+          if (row < n) {
+            if (out_mode == 0) {
+              if (c < p) Out[(int64_t)(c / B) * stride + row * B + (c % B)] = to_storage<TO, double>(acc[t][reg]);
+            } else if (c < c_out) {
+              Out[row * c_out + c] = to_storage<TO, double>(acc[t][reg]);
             }
           }
-#pragma unroll
-          for (int c0 = 0; c0 < B; c0 += VEC)
-            store_vec<TO, VEC>(Out + ob * stride + r * B + c0, acc + c0);
         }
       }
-      return;
     }
-  }
-  // packed n x c_out
-  for (int o = 0; o < c_out; ++o) {
-    double acc = 0.0;
-#pragma unroll
-    for (int t = 0; t < MAXM; ++t)
-      if (t < m) acc = fma((double)v[t], Ys[t * p + o], acc);
-    Out[r * c_out + o] = to_storage<TO, double>(acc);
   }
 }
 
@@ -484,34 +480,25 @@ template <typename T, typename TO = T>
 fe_status rotate_t(void* Out, int32_t out_mode, int32_t c_out, int64_t n, int32_t b,
                    const void* V, int32_t nblk, int64_t stride, const double* Y, int32_t p,
                    hipStream_t s) {
-  const int64_t g = (n + 255) / 256;
   const int m = nblk * b;
-  const size_t lds = (size_t)m * p * sizeof(double);
-  constexpr int kMaxRows = sizeof(T) == 8 ? kRotMax : kRotRows;
-  if (p > kRotMax || m > kMaxRows || lds > 64 * 1024)
+  const int p16 = (p + 15) / 16 * 16;
+  const size_t lds = (size_t)m * p16 * sizeof(double);
+  if (p > kRotMax || m > kRotRows || lds > 64 * 1024)
     return fail(FE_EUNSUPPORTED, "rotate: m=%d (max %d), p=%d (max %d) or m*p too large", m,
-                kMaxRows, p, kRotMax);
+                kRotRows, p, kRotMax);
+  const int64_t groups = (n + 15) / 16;
+  const uint32_t grid = (uint32_t)std::max<int64_t>(1, std::min<int64_t>((groups + 3) / 4, 8192));
   TO* O = static_cast<TO*>(Out);
   const T* Vp = static_cast<const T*>(V);
-#define FE_ROT(BB, MM)                                                                            \
-  case BB:                                                                                        \
-    hipLaunchKernelGGL((rotate_kernel<T, TO, BB, MM>), dim3((uint32_t)g), dim3(256), lds, s, O,  \
-                       out_mode, c_out, n, Vp, nblk, stride, Y, p);                              \
+#define FE_ROT(BB)                                                                               \
+  case BB:                                                                                       \
+    hipLaunchKernelGGL((rotate_kernel<T, TO, BB>), dim3(grid), dim3(256), lds, s, O, out_mode,   \
+                       c_out, n, Vp, nblk, stride, Y, p, p16);                                  \
     break;
-  if (m <= kRotMax) {
-    switch (b) {
-      FE_ROT(1, kRotMax) FE_ROT(2, kRotMax) FE_ROT(4, kRotMax) FE_ROT(8, kRotMax)
-      FE_ROT(16, kRotMax)
-      default:
-        return fail(FE_EUNSUPPORTED, "rotate: block %d not in {1,2,4,8,16}", b);
-    }
-  } else if constexpr (sizeof(T) < 8) {
-    switch (b) {
-      FE_ROT(1, kRotRows) FE_ROT(2, kRotRows) FE_ROT(4, kRotRows) FE_ROT(8, kRotRows)
-      FE_ROT(16, kRotRows)
-      default:
-        return fail(FE_EUNSUPPORTED, "rotate: block %d not in {1,2,4,8,16}", b);
-    }
+  switch (b) {
+    FE_ROT(1) FE_ROT(2) FE_ROT(4) FE_ROT(8) FE_ROT(16)
+    default:
+      return fail(FE_EUNSUPPORTED, "rotate: block %d not in {1,2,4,8,16}", b);
   }
 #undef FE_ROT
   FE_HIP(hipGetLastError());

@@ -645,8 +645,6 @@ extern "C" fe_status fe_krylov_schur(const fe_csr* A, int32_t nev, int32_t block
   const int p = m - block * std::max(1, (m - nev) / (2 * block));
   if (m > 128 || p > 64 || nev > 64 || (size_t)m * p * 8 > 64 * 1024)
     return fail(FE_EUNSUPPORTED, "fe_krylov_schur: m=%d keeps p=%d (limits m<=128, p<=64)", m, p);
-  if (m > 64 && o.dt == FE_F64)
-    return fail(FE_EUNSUPPORTED, "fe_krylov_schur: m=%d with FP64 storage (limit 64)", m);
   if (block != 1 && block != 2 && block != 4 && block != 8 && block != 16)
     return fail(FE_EUNSUPPORTED, "fe_krylov_schur: block must be 1, 2, 4, 8 or 16");
   if ((int64_t)m + block > A->n) return fail(FE_EINVAL, "fe_krylov_schur: m + block > n");

@@ -185,10 +185,24 @@ def test_subspace_beyond_64_fp32(fe, m):
     check_vectors(rp, ci, r)
 
 
+def test_subspace_beyond_64_fp64_matches_oracle(fe):
+    """FP64 storage at m = 96: the same products and eigenvalues as the oracle."""
+    g = S.chung_lu_edges(20000, alpha=2.2, mean_deg=12, seed=21)
+    A, rp, ci = setup(fe, g)
+    X0 = S.normal((A.n, 8), seed=4)
+    ref = oracle_ks(rp, ci, A.n, 8, 8, 96, 1e-10, X0)
+    r = fe.fe_krylov_schur(A, 8, 8, 96, 1e-10, dtype=torch.float64,
+                           start=torch.tensor(X0, device="cuda"))
+    assert r.status == fe.FE_OK and ref.converged
+    assert np.allclose(r.evals, ref.evals, rtol=1e-10, atol=0)
+    assert r.spmm_calls == ref.spmm_calls
+    check_vectors(rp, ci, r)
+
+
 def test_subspace_limits(fe):
     g = S.rmat_edges(12, seed=1)
     A, rp, ci = setup(fe, g)
-    for args, dt in [((8, 8, 96), torch.float64), ((8, 8, 128), torch.float32)]:
+    for args in [(8, 8, 128), (8, 16, 144)]:  # keeps p = 72 > 64; m > 128
         with pytest.raises(fe.FeError) as e:
-            fe.fe_krylov_schur(A, *args, 1e-8, dtype=dt)
+            fe.fe_krylov_schur(A, *args, 1e-8, dtype=torch.float32)
         assert e.value.status == fe.FE_EUNSUPPORTED
