@@ -121,6 +121,149 @@ __global__ __launch_bounds__(kGramWG) void gram_kernel(const T* __restrict__ V, 
   }
 }
 
+// Same contraction for b a multiple of 4, with 16-byte row loads: lane x of
+// each quad loads the four consecutive columns of row r0 + 4x + kk that its
+// quad needs, and a 4 x 4 transpose across the quad (two DPP quad_perm
+// stages, 32-bit lanes) hands every lane the operand the plain kernel would
+// have loaded with four separate element loads.  Four times fewer load
+// instructions; the texture-address unit was 64% busy with element loads.
+template <int CTRL>
+__device__ __forceinline__ float quad_dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_dpp(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(u & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// v[c] of quad lane x becomes v[c] of lane c before the call (4 x 4 transpose):
+// stage 1 exchanges, between lanes x and x^2, the components c whose bit 1
+// differs from x's; stage 2 does the same for bit 0 between x and x^1.
+template <typename A>
+__device__ __forceinline__ void quad_transpose(A (&v)[4], int x) {
+  {
+    const A a0 = quad_dpp<0x4E>(v[0]), a1 = quad_dpp<0x4E>(v[1]);  // quad_perm 2,3,0,1
+    const A a2 = quad_dpp<0x4E>(v[2]), a3 = quad_dpp<0x4E>(v[3]);
+    const bool hi = x & 2;
+    v[0] = hi ? a2 : v[0];
+    v[1] = hi ? a3 : v[1];
+    v[2] = hi ? v[2] : a0;
+    v[3] = hi ? v[3] : a1;
+  }
+  {
+    const A a0 = quad_dpp<0xB1>(v[0]), a1 = quad_dpp<0xB1>(v[1]);  // quad_perm 1,0,3,2
+    const A a2 = quad_dpp<0xB1>(v[2]), a3 = quad_dpp<0xB1>(v[3]);
+    const bool odd = x & 1;
+    v[0] = odd ? a1 : v[0];
+    v[1] = odd ? v[1] : a0;
+    v[2] = odd ? a3 : v[2];
+    v[3] = odd ? v[3] : a2;
+  }
+}
+
+template <typename T, int NQG>
+__global__ __launch_bounds__(kGramWG) void gram_wide_kernel(const T* __restrict__ V,
+                                                            int64_t stride,
+                                                            const T* __restrict__ W, int64_t n,
+                                                            int32_t b, int32_t k,
+                                                            int64_t rows_per_wg,
+                                                            double* __restrict__ partials) {
+  using A = typename Acc<T>::type;
+  constexpr int VEC = 16 / sizeof(T) < 4 ? 16 / sizeof(T) : 4;  // 4 elements per load group
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kk = lane >> 4, blk = (lane >> 2) & 3, x = lane & 3;
+  const int p_base = blockIdx.y * (16 * kGramPG);
+  const int q_base = blockIdx.z * (4 * NQG);
+  const int npg = min(kGramPG, (k - p_base + 15) / 16);
+  const int nqg = min(NQG, (b - q_base + 3) / 4);
+  // column group of this lane's quad: 4 consecutive columns inside one block
+  int64_t aoff[kGramPG];
+  bool aval[kGramPG];
+#pragma unroll
+  for (int pg = 0; pg < kGramPG; ++pg) {
+    const int c0 = p_base + pg * 16 + 4 * blk;
+    aval[pg] = c0 < k;
+    aoff[pg] = aval[pg] ? (int64_t)(c0 / b) * stride + (c0 % b) : 0;
+  }
+  int boff[NQG];
+  bool bval[NQG];
+#pragma unroll
+  for (int qg = 0; qg < NQG; ++qg) {
+    const int q0 = q_base + qg * 4;
+    bval[qg] = q0 < b;
+    boff[qg] = bval[qg] ? q0 : 0;
+  }
+  double acc[kGramPG][NQG];
+#pragma unroll
+  for (int pg = 0; pg < kGramPG; ++pg)
+#pragma unroll
+    for (int qg = 0; qg < NQG; ++qg) acc[pg][qg] = 0.0;
+
+  const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r_end = min(n, r_begin + rows_per_wg);
+  for (int64_t r0 = r_begin + wave * kGramRowsPerIter; r0 < r_end;
+       r0 += (kGramWG / 64) * kGramRowsPerIter) {
+    const int64_t row = r0 + 4 * x + kk;  // the row this lane loads
+    const bool rv = row < r_end;
+    const int64_t rb = (rv ? row : r_end - 1) * b;
+    double a[4][kGramPG], bb[4][NQG];
+#pragma unroll
+    for (int pg = 0; pg < kGramPG; ++pg) {
+      A v[4];
+#pragma unroll
+      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(V + aoff[pg] + rb + c, v + c);
+      const bool ok = rv && aval[pg];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = ok ? v[c] : (A)0;
+      quad_transpose(v, x);  // v[u] = element (row r0 + 4u + kk, column c0 + x)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u][pg] = (double)v[u];
+    }
+#pragma unroll
+    for (int qg = 0; qg < NQG; ++qg) {
+      A v[4];
+#pragma unroll
+      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(W + rb + boff[qg] + c, v + c);
+      const bool ok = rv && bval[qg];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = ok ? v[c] : (A)0;
+      quad_transpose(v, x);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) bb[u][qg] = (double)v[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int pg = 0; pg < kGramPG; ++pg)
+        if (pg < npg)
+#pragma unroll
+          for (int qg = 0; qg < NQG; ++qg)
+            if (qg < nqg)
+              acc[pg][qg] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u][pg], bb[u][qg], acc[pg][qg],
+                                                               0, 0, 0);
+  }
+  __shared__ double red[kGramPG][NQG][64];
+  for (int w = 0; w < kGramWG / 64; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int pg = 0; pg < kGramPG; ++pg)
+#pragma unroll
+        for (int qg = 0; qg < NQG; ++qg)
+          red[pg][qg][lane] = (w == 0 ? 0.0 : red[pg][qg][lane]) + acc[pg][qg];
+    }
+    __syncthreads();
+  }
+  double* out = partials + (int64_t)blockIdx.x * k * b;
+  for (int idx = threadIdx.x; idx < kGramPG * NQG * 64; idx += kGramWG) {
+    const int l = idx & 63, qg = (idx >> 6) % NQG, pg = (idx >> 6) / NQG;
+    const int i = l >> 4, bl = (l >> 2) & 3, j = l & 3;
+    const int p = p_base + pg * 16 + 4 * bl + i, q = q_base + qg * 4 + j;
+    if (p < k && q < b) out[(int64_t)p * b + q] = red[pg][qg][l];
+  }
+}
+
 // C[e] = alpha * sum over partial sets x (fixed order: strided lanes, then group order)
 __global__ __launch_bounds__(1024) void reduce_partials(const double* __restrict__ partials,
                                                         int32_t nsets, int32_t len, double alpha,
@@ -159,15 +302,21 @@ fe_status gram_t(const void* V, int32_t nblk, int64_t stride, const void* W, int
   dim3 grid(gx, gy, gz);
   const T* Vp = static_cast<const T*>(V);
   const T* Wp = static_cast<const T*>(W);
-  if (b <= 4)
-    hipLaunchKernelGGL((gram_kernel<T, 1>), grid, dim3(kGramWG), 0, s, Vp, stride, Wp, n, b, k,
-                       rows_per_wg, partials);
-  else if (b <= 8)
-    hipLaunchKernelGGL((gram_kernel<T, 2>), grid, dim3(kGramWG), 0, s, Vp, stride, Wp, n, b, k,
-                       rows_per_wg, partials);
-  else
-    hipLaunchKernelGGL((gram_kernel<T, 4>), grid, dim3(kGramWG), 0, s, Vp, stride, Wp, n, b, k,
-                       rows_per_wg, partials);
+#define FE_GRAM(KERNEL, Q)                                                                    \
+  hipLaunchKernelGGL((KERNEL<T, Q>), grid, dim3(kGramWG), 0, s, Vp, stride, Wp, n, b, k,      \
+                     rows_per_wg, partials)
+  if (b % 4 == 0) {  // every 4-column group lies inside one block: 16-byte row loads
+    if (b == 4) FE_GRAM(gram_wide_kernel, 1);
+    else if (b == 8) FE_GRAM(gram_wide_kernel, 2);
+    else FE_GRAM(gram_wide_kernel, 4);
+  } else if (b <= 4) {
+    FE_GRAM(gram_kernel, 1);
+  } else if (b <= 8) {
+    FE_GRAM(gram_kernel, 2);
+  } else {
+    FE_GRAM(gram_kernel, 4);
+  }
+#undef FE_GRAM
   FE_HIP(hipGetLastError());
   const int len = k * b;
   hipLaunchKernelGGL(reduce_partials, dim3((len + 63) / 64), dim3(1024), 0, s, partials, gx, len,
