@@ -852,6 +852,132 @@ fe_status combine_launch(double* Out, int32_t c, int64_t n, int32_t b, const voi
   return fail(FE_EINVAL, "combine: bad dtype");
 }
 
+// ------------------------------------------- block QR factors on the device
+// The small factorisations of one orthogonalisation step, done on the GPU so
+// that the common case (no dependent column) needs no host round trip.  One
+// workgroup; the b x b Gram of the step is formed in parallel, then thread 0
+// runs exactly the host's serial FP64 recurrences (same operations, same
+// order), so the factors are bitwise those of the host path.
+constexpr int kCholMaxB = 16;
+
+// Upper-triangular inverse, column by column (same recurrence as the host).
+__device__ void dev_inv_upper(int nb, const double* R, double* Ri) {
+  for (int i = 0; i < nb * nb; ++i) Ri[i] = 0.0;
+  for (int j = 0; j < nb; ++j) {
+    Ri[j * nb + j] = 1.0 / R[j * nb + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double acc = 0.0;
+      for (int t = i + 1; t <= j; ++t) acc += R[i * nb + t] * Ri[t * nb + j];
+      Ri[i * nb + j] = -acc / R[i * nb + i];
+    }
+  }
+}
+
+// First pass.  C1, C2: (k + b) x b Grams of [V W] with W before / after the
+// first projection.  Writes C = C1 + C2 (rows < k) to rec, the factor R1 of
+// G = W2^T W2 = C2[k:] - C2[:k]^T C2[:k] to R1, M = R1^-1, and *flag = 1 when a
+// column is dependent (norm after projection <= eta x norm before).
+__global__ __launch_bounds__(256) void chol_first_kernel(const double* __restrict__ C1,
+                                                         const double* __restrict__ C2, int k,
+                                                         int b, double eta, double* __restrict__ rec,
+                                                         double* __restrict__ R1,
+                                                         double* __restrict__ M,
+                                                         double* __restrict__ flag) {
+  __shared__ double G[kCholMaxB * kCholMaxB], R[kCholMaxB * kCholMaxB];
+  for (int e = threadIdx.x; e < k * b; e += blockDim.x) rec[e] = C1[e] + C2[e];
+  for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+    const int i = e / b, j = e % b;
+    double g = C2[(k + i) * b + j];
+    for (int t = 0; t < k; ++t) g -= C2[t * b + i] * C2[t * b + j];
+    G[e] = g;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  bool dep = false;
+  for (int i = 0; i < b * b; ++i) R[i] = 0.0;
+  for (int j = 0; j < b && !dep; ++j) {
+    double d = G[j * b + j];
+    for (int i = 0; i < j; ++i) d -= R[i * b + j] * R[i * b + j];
+    const double nbj = sqrt(fmax(0.0, C1[(k + j) * b + j]));
+    const double thr = eta * nbj;
+    if (!(d > thr * thr) || !(d > 0.0)) {
+      dep = true;
+      break;
+    }
+    const double rjj = sqrt(d);
+    R[j * b + j] = rjj;
+    for (int l = j + 1; l < b; ++l) {
+      double g = G[j * b + l];
+      for (int i = 0; i < j; ++i) g -= R[i * b + j] * R[i * b + l];
+      R[j * b + l] = g / rjj;
+    }
+  }
+  for (int i = 0; i < b * b; ++i) R1[i] = R[i];
+  if (dep) {
+    for (int i = 0; i < b * b; ++i) M[i] = (i / b == i % b) ? 1.0 : 0.0;
+    flag[0] = 1.0;
+  } else {
+    dev_inv_upper(b, R, M);
+    flag[0] = 0.0;
+  }
+}
+
+// Second pass (Cholesky QR of the right-multiplied block): G = W^T W (b x b),
+// Rp its Cholesky factor, M = Rp^-1, recR = Rp R1; flag += 2 on failure.
+__global__ __launch_bounds__(64) void chol_second_kernel(const double* __restrict__ G, int b,
+                                                         const double* __restrict__ R1,
+                                                         double* __restrict__ M,
+                                                         double* __restrict__ recR,
+                                                         double* __restrict__ flag) {
+  if (threadIdx.x != 0) return;
+  double Rp[kCholMaxB * kCholMaxB];
+  for (int i = 0; i < b * b; ++i) Rp[i] = 0.0;
+  bool ok = true;
+  for (int j = 0; j < b && ok; ++j) {
+    double d = G[j * b + j];
+    for (int i = 0; i < j; ++i) d -= Rp[i * b + j] * Rp[i * b + j];
+    if (!(d > 0.0)) {
+      ok = false;
+      break;
+    }
+    Rp[j * b + j] = sqrt(d);
+    for (int l = j + 1; l < b; ++l) {
+      double g = G[j * b + l];
+      for (int i = 0; i < j; ++i) g -= Rp[i * b + j] * Rp[i * b + l];
+      Rp[j * b + l] = g / Rp[j * b + j];
+    }
+  }
+  if (!ok) {
+    for (int i = 0; i < b * b; ++i) M[i] = (i / b == i % b) ? 1.0 : 0.0;
+    flag[0] += 2.0;
+    return;
+  }
+  dev_inv_upper(b, Rp, M);
+  for (int i = 0; i < b; ++i)
+    for (int j = 0; j < b; ++j) {
+      double acc = 0.0;
+      for (int t = 0; t < b; ++t) acc += Rp[i * b + t] * R1[t * b + j];
+      recR[i * b + j] = acc;
+    }
+}
+
+fe_status chol_first_launch(const double* C1, const double* C2, int32_t k, int32_t b, double eta,
+                            double* rec, double* R1, double* M, double* flag, hipStream_t s) {
+  if (b > kCholMaxB) return fail(FE_EUNSUPPORTED, "chol: block %d > %d", b, kCholMaxB);
+  hipLaunchKernelGGL(chol_first_kernel, dim3(1), dim3(256), 0, s, C1, C2, k, b, eta, rec, R1, M,
+                     flag);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status chol_second_launch(const double* G, int32_t b, const double* R1, double* M,
+                             double* recR, double* flag, hipStream_t s) {
+  if (b > kCholMaxB) return fail(FE_EUNSUPPORTED, "chol: block %d > %d", b, kCholMaxB);
+  hipLaunchKernelGGL(chol_second_kernel, dim3(1), dim3(64), 0, s, G, b, R1, M, recR, flag);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
 size_t resid_partials_doubles(int64_t n, int32_t c) { return (size_t)resid_sets(n) * 3 * c; }
 
 fe_status resid_launch(const double* AX, const double* X, int64_t n, int32_t c,

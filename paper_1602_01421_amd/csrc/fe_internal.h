@@ -82,6 +82,14 @@ size_t gram_partials_doubles(int64_t n, int32_t k, int32_t b);
 fe_status gram_launch(const void* V, int32_t nblk, int64_t blk_stride, const void* W, int64_t n,
                       int32_t b, fe_dtype dt, double alpha, double* C, double* partials,
                       hipStream_t s);
+// Block QR factors of one orthogonalisation step on the device (b <= 16):
+// first pass from the two Grams C1, C2 ((k+b) x b): rec = C1 + C2 (k x b),
+// R1 = chol(W2^T W2), M = R1^-1, flag = 1 on a dependent column; second pass
+// from G = W^T W: M = chol(G)^-1, recR = chol(G) R1, flag += 2 on failure.
+fe_status chol_first_launch(const double* C1, const double* C2, int32_t k, int32_t b, double eta,
+                            double* rec, double* R1, double* M, double* flag, hipStream_t s);
+fe_status chol_second_launch(const double* G, int32_t b, const double* R1, double* M,
+                             double* recR, double* flag, hipStream_t s);
 // W <- W - V C (C: k x b FP64, k = nblk*b <= 64, b in {1,2,4,8,16}) and, in
 // the same pass, Cout ((k+b) x b) = [V W']^T W' of the rounded result;
 // partials sized by gram_partials_doubles(n, k + b, b).

@@ -155,6 +155,10 @@ class Solver {
   double *dPart = nullptr, *dPartRes = nullptr;
   double *hC1 = nullptr, *hC2 = nullptr, *hG = nullptr, *hM = nullptr, *hY = nullptr,
          *hSums = nullptr, *hTheta = nullptr;
+  // Per-step records of the device-side orthogonalisation (one slot per
+  // block): C (k x b, stride m*b), R (b x b), status flag.
+  double *dRec = nullptr, *hRec = nullptr, *dR1 = nullptr;
+  size_t rec_stride = 0;
   DevBuf dev;
   HostBuf host;
   Prof prof;
@@ -237,6 +241,10 @@ class Solver {
     FE_TRY(host.get(&hY, m * m));
     FE_TRY(host.get(&hSums, 3 * 64));
     FE_TRY(host.get(&hTheta, 64));
+    rec_stride = (size_t)m * b + (size_t)b * b + 1;
+    FE_TRY(dev.get((void**)&dRec, sizeof(double) * rec_stride * (m / b + 1)));
+    FE_TRY(host.get(&hRec, rec_stride * (m / b + 1)));
+    FE_TRY(dev.get((void**)&dR1, sizeof(double) * b * b));
     T.assign((size_t)m * m, 0.0);
     Bk.assign((size_t)b * m, 0.0);
     return FE_OK;
@@ -291,6 +299,48 @@ class Solver {
     bytes[P_GRAM] += (double)n * b * es;
     FE_HIP(hipMemcpyAsync(hG, dC, sizeof(double) * b * b, hipMemcpyDeviceToHost, s));
     return sync();
+  }
+
+  // orth_block without host round trips, for the common case: the same
+  // kernels, with the rank-revealing Cholesky, the triangular inverses and the
+  // second Cholesky QR pass done by small device kernels (bitwise the host's
+  // arithmetic).  C, R and a status flag go to the step's record; a nonzero
+  // flag (dependent column, failed factorisation) makes the caller redo the
+  // step with orth_block, which handles refills.
+  fe_status orth_fast(int wb, double* rec) {
+    const int nk = wb;
+    const int k = nk * b;
+    void* W = blk(wb);
+    double* dC1 = dC;
+    double* dC2 = dC + (size_t)(k + b) * b;
+    double* flag = rec + (size_t)m * b + (size_t)b * b;
+    FE_TRY(gram(nk + 1, W, dC1));
+    FE_TRY(update(W, V, nk, dC1, -1.0, 1.0));
+    FE_TRY(gram(nk + 1, W, dC2));
+    FE_TRY(update(W, V, nk, dC2, -1.0, 1.0));
+    FE_TRY(chol_first_launch(dC1, dC2, k, b, eta, rec, dR1, dM, flag, s));
+    FE_TRY(update(W, W, 1, dM, 1.0, 0.0));
+    prof.begin(P_GRAM);
+    FE_TRY(gram_launch(W, 1, stride, W, n, b, dt, 1.0, dC, dPart, s));
+    prof.end();
+    ++gram_calls;
+    bytes[P_GRAM] += (double)n * b * es;
+    FE_TRY(chol_second_launch(dC, b, dR1, dM, rec + (size_t)m * b, flag, s));
+    return update(W, W, 1, dM, 1.0, 0.0);
+  }
+
+  // T gets C as the new columns k-b..k-1 (and their mirror), Bk the new R.
+  void absorb(int k, const double* C, const double* R) {
+    auto th = clk::now();
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < b; ++j) {
+        T[(size_t)i * m + (k - b + j)] = C[(size_t)i * b + j];
+        T[(size_t)(k - b + j) * m + i] = C[(size_t)i * b + j];
+      }
+    std::fill(Bk.begin(), Bk.end(), 0.0);
+    for (int i = 0; i < b; ++i)
+      for (int j = 0; j < b; ++j) Bk[(size_t)i * m + (k - b + j)] = R[(size_t)i * b + j];
+    t_host += secs(th, clk::now());
   }
 
   // Orthogonalise W (block wb) against V[:, :k] (blocks 0..k/b-1, k = wb*b) and
@@ -459,25 +509,56 @@ class Solver {
     std::vector<double> theta(m), Y((size_t)m * m), rho(m);
     bool converged = false;
     int nconv = 0;
+    struct Pending {
+      int wb, step0;
+    };
+    std::vector<Pending> pend;
     for (;;) {
-      while (k < m) {
-        k += b;
-        const int wb = k / b;
-        FE_TRY(spmm(blk(wb - 1), blk(wb), b));
-        ++spmm_calls;
-        if (dt != dt_final) ++spmm_low;
-        ++step;
-        FE_TRY(orth_block(wb, C, R));
-        auto th = clk::now();
-        for (int i = 0; i < k; ++i)
-          for (int j = 0; j < b; ++j) {
-            T[(size_t)i * m + (k - b + j)] = C[(size_t)i * b + j];
-            T[(size_t)(k - b + j) * m + i] = C[(size_t)i * b + j];
+      // Expansion.  Steps run with device-side factors and are checked when
+      // the expansion ends; the first flagged step (and every later one) is
+      // discarded and redone from its product on, that step on the host path.
+      int force_host = -1;
+      for (bool redo = true; redo;) {
+        redo = false;
+        while (k < m) {
+          k += b;
+          const int wb = k / b;
+          const int step0 = step;
+          FE_TRY(spmm(blk(wb - 1), blk(wb), b));
+          ++spmm_calls;
+          if (dt != dt_final) ++spmm_low;
+          ++step;
+          if (wb == force_host) {
+            FE_TRY(orth_block(wb, C, R));
+            absorb(k, C.data(), R.data());
+          } else {
+            FE_TRY(orth_fast(wb, dRec + (size_t)wb * rec_stride));
+            pend.push_back({wb, step0});
           }
-        std::fill(Bk.begin(), Bk.end(), 0.0);
-        for (int i = 0; i < b; ++i)
-          for (int j = 0; j < b; ++j) Bk[(size_t)i * m + (k - b + j)] = R[(size_t)i * b + j];
-        t_host += secs(th, clk::now());
+        }
+        if (pend.empty()) break;
+        const int w0 = pend.front().wb, w1 = pend.back().wb;
+        FE_HIP(hipMemcpyAsync(hRec + (size_t)w0 * rec_stride, dRec + (size_t)w0 * rec_stride,
+                              sizeof(double) * rec_stride * (w1 - w0 + 1),
+                              hipMemcpyDeviceToHost, s));
+        FE_TRY(sync());
+        for (size_t i = 0; i < pend.size(); ++i) {
+          const Pending& P = pend[i];
+          const double* rec = hRec + (size_t)P.wb * rec_stride;
+          if (rec[(size_t)m * b + (size_t)b * b] != 0.0) {
+            const int dropped = (int)(pend.size() - i);
+            spmm_calls -= dropped;
+            spmm_cols -= dropped * b;
+            if (dt != dt_final) spmm_low -= dropped;
+            k = (P.wb - 1) * b;
+            step = P.step0;
+            force_host = P.wb;
+            redo = true;
+            break;
+          }
+          absorb(P.wb * b, rec, rec + (size_t)m * b);
+        }
+        pend.clear();
       }
       // Rayleigh-Ritz on the symmetric part of T
       auto th = clk::now();
