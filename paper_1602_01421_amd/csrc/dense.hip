@@ -860,17 +860,43 @@ fe_status combine_launch(double* Out, int32_t c, int64_t n, int32_t b, const voi
 // order), so the factors are bitwise those of the host path.
 constexpr int kCholMaxB = 16;
 
-// Upper-triangular inverse, column by column (same recurrence as the host).
-__device__ void dev_inv_upper(int nb, const double* R, double* Ri) {
-  for (int i = 0; i < nb * nb; ++i) Ri[i] = 0.0;
-  for (int j = 0; j < nb; ++j) {
-    Ri[j * nb + j] = 1.0 / R[j * nb + j];
-    for (int i = j - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int t = i + 1; t <= j; ++t) acc += R[i * nb + t] * Ri[t * nb + j];
-      Ri[i * nb + j] = -acc / R[i * nb + i];
+// Column j of the inverse of the upper-triangular R (nb x nb), the host's
+// recurrence; columns are independent, so threads take one each.
+__device__ void dev_inv_upper_col(int nb, const double* R, double* Ri, int j) {
+  for (int i = j + 1; i < nb; ++i) Ri[i * nb + j] = 0.0;
+  Ri[j * nb + j] = 1.0 / R[j * nb + j];
+  for (int i = j - 1; i >= 0; --i) {
+    double acc = 0.0;
+    for (int t = i + 1; t <= j; ++t) acc += R[i * nb + t] * Ri[t * nb + j];
+    Ri[i * nb + j] = -acc / R[i * nb + i];
+  }
+}
+
+// Thread 0 factors G (b x b, LDS) into R (LDS) with the dependence test of the
+// first pass (eta > 0, column norms before projection from C1) or plainly
+// (eta < 0); returns through *ok.
+__device__ void dev_chol(const double* G, double* R, int b, double eta, const double* C1, int k,
+                         int* ok) {
+  for (int i = 0; i < b * b; ++i) R[i] = 0.0;
+  int good = 1;
+  for (int j = 0; j < b && good; ++j) {
+    double d = G[j * b + j];
+    for (int i = 0; i < j; ++i) d -= R[i * b + j] * R[i * b + j];
+    double thr = 0.0;
+    if (eta > 0.0) thr = eta * sqrt(fmax(0.0, C1[(k + j) * b + j]));
+    if (!(d > thr * thr) || !(d > 0.0)) {
+      good = 0;
+      break;
+    }
+    const double rjj = sqrt(d);
+    R[j * b + j] = rjj;
+    for (int l = j + 1; l < b; ++l) {
+      double g = G[j * b + l];
+      for (int i = 0; i < j; ++i) g -= R[i * b + j] * R[i * b + l];
+      R[j * b + l] = g / rjj;
     }
   }
+  *ok = good;
 }
 
 // First pass.  C1, C2: (k + b) x b Grams of [V W] with W before / after the
@@ -884,6 +910,7 @@ __global__ __launch_bounds__(256) void chol_first_kernel(const double* __restric
                                                          double* __restrict__ M,
                                                          double* __restrict__ flag) {
   __shared__ double G[kCholMaxB * kCholMaxB], R[kCholMaxB * kCholMaxB];
+  __shared__ int ok;
   for (int e = threadIdx.x; e < k * b; e += blockDim.x) rec[e] = C1[e] + C2[e];
   for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
     const int i = e / b, j = e % b;
@@ -892,73 +919,42 @@ __global__ __launch_bounds__(256) void chol_first_kernel(const double* __restric
     G[e] = g;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  bool dep = false;
-  for (int i = 0; i < b * b; ++i) R[i] = 0.0;
-  for (int j = 0; j < b && !dep; ++j) {
-    double d = G[j * b + j];
-    for (int i = 0; i < j; ++i) d -= R[i * b + j] * R[i * b + j];
-    const double nbj = sqrt(fmax(0.0, C1[(k + j) * b + j]));
-    const double thr = eta * nbj;
-    if (!(d > thr * thr) || !(d > 0.0)) {
-      dep = true;
-      break;
-    }
-    const double rjj = sqrt(d);
-    R[j * b + j] = rjj;
-    for (int l = j + 1; l < b; ++l) {
-      double g = G[j * b + l];
-      for (int i = 0; i < j; ++i) g -= R[i * b + j] * R[i * b + l];
-      R[j * b + l] = g / rjj;
-    }
-  }
-  for (int i = 0; i < b * b; ++i) R1[i] = R[i];
-  if (dep) {
-    for (int i = 0; i < b * b; ++i) M[i] = (i / b == i % b) ? 1.0 : 0.0;
-    flag[0] = 1.0;
+  if (threadIdx.x == 0) dev_chol(G, R, b, eta, C1, k, &ok);
+  __syncthreads();
+  for (int e = threadIdx.x; e < b * b; e += blockDim.x) R1[e] = R[e];
+  if (ok) {
+    if ((int)threadIdx.x < b) dev_inv_upper_col(b, R, M, threadIdx.x);
   } else {
-    dev_inv_upper(b, R, M);
-    flag[0] = 0.0;
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) M[e] = (e / b == e % b) ? 1.0 : 0.0;
   }
+  if (threadIdx.x == 0) flag[0] = ok ? 0.0 : 1.0;
 }
 
 // Second pass (Cholesky QR of the right-multiplied block): G = W^T W (b x b),
 // Rp its Cholesky factor, M = Rp^-1, recR = Rp R1; flag += 2 on failure.
-__global__ __launch_bounds__(64) void chol_second_kernel(const double* __restrict__ G, int b,
-                                                         const double* __restrict__ R1,
-                                                         double* __restrict__ M,
-                                                         double* __restrict__ recR,
-                                                         double* __restrict__ flag) {
-  if (threadIdx.x != 0) return;
-  double Rp[kCholMaxB * kCholMaxB];
-  for (int i = 0; i < b * b; ++i) Rp[i] = 0.0;
-  bool ok = true;
-  for (int j = 0; j < b && ok; ++j) {
-    double d = G[j * b + j];
-    for (int i = 0; i < j; ++i) d -= Rp[i * b + j] * Rp[i * b + j];
-    if (!(d > 0.0)) {
-      ok = false;
-      break;
-    }
-    Rp[j * b + j] = sqrt(d);
-    for (int l = j + 1; l < b; ++l) {
-      double g = G[j * b + l];
-      for (int i = 0; i < j; ++i) g -= Rp[i * b + j] * Rp[i * b + l];
-      Rp[j * b + l] = g / Rp[j * b + j];
-    }
-  }
+__global__ __launch_bounds__(256) void chol_second_kernel(const double* __restrict__ G, int b,
+                                                          const double* __restrict__ R1,
+                                                          double* __restrict__ M,
+                                                          double* __restrict__ recR,
+                                                          double* __restrict__ flag) {
+  __shared__ double Gs[kCholMaxB * kCholMaxB], Rp[kCholMaxB * kCholMaxB];
+  __shared__ int ok;
+  for (int e = threadIdx.x; e < b * b; e += blockDim.x) Gs[e] = G[e];
+  __syncthreads();
+  if (threadIdx.x == 0) dev_chol(Gs, Rp, b, -1.0, nullptr, 0, &ok);
+  __syncthreads();
   if (!ok) {
-    for (int i = 0; i < b * b; ++i) M[i] = (i / b == i % b) ? 1.0 : 0.0;
-    flag[0] += 2.0;
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) M[e] = (e / b == e % b) ? 1.0 : 0.0;
+    if (threadIdx.x == 0) flag[0] += 2.0;
     return;
   }
-  dev_inv_upper(b, Rp, M);
-  for (int i = 0; i < b; ++i)
-    for (int j = 0; j < b; ++j) {
-      double acc = 0.0;
-      for (int t = 0; t < b; ++t) acc += Rp[i * b + t] * R1[t * b + j];
-      recR[i * b + j] = acc;
-    }
+  if ((int)threadIdx.x < b) dev_inv_upper_col(b, Rp, M, threadIdx.x);
+  for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+    const int i = e / b, j = e % b;
+    double acc = 0.0;
+    for (int t = 0; t < b; ++t) acc += Rp[i * b + t] * R1[t * b + j];
+    recR[e] = acc;
+  }
 }
 
 fe_status chol_first_launch(const double* C1, const double* C2, int32_t k, int32_t b, double eta,
@@ -973,7 +969,7 @@ fe_status chol_first_launch(const double* C1, const double* C2, int32_t k, int32
 fe_status chol_second_launch(const double* G, int32_t b, const double* R1, double* M,
                              double* recR, double* flag, hipStream_t s) {
   if (b > kCholMaxB) return fail(FE_EUNSUPPORTED, "chol: block %d > %d", b, kCholMaxB);
-  hipLaunchKernelGGL(chol_second_kernel, dim3(1), dim3(64), 0, s, G, b, R1, M, recR, flag);
+  hipLaunchKernelGGL(chol_second_kernel, dim3(1), dim3(256), 0, s, G, b, R1, M, recR, flag);
   FE_HIP(hipGetLastError());
   return FE_OK;
 }
