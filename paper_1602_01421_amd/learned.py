@@ -104,6 +104,18 @@ def _labelled(args, first_seed, count, t0, tag, budget):
     return data
 
 
+def val_loss(net, A, z, V):
+    """Loss on one graph; 1 (the loss of an output orthogonal to V) when the
+    output is rank deficient."""
+    from . import fe as F
+    try:
+        return net.backward(A, z, V)[0]
+    except F.FeError as e:
+        if e.status != F.FE_EBREAKDOWN:
+            raise
+        return 1.0
+
+
 def train(args):
     """Label the training and validation graphs, then run Adam epochs.
 
@@ -116,6 +128,8 @@ def train(args):
     from . import fe as F
     torch = _torch()
     net = F.Gnn(seed=args.init_seed, compute=args.compute)
+    if args.init_weights:  # continue from trained weights (fresh Adam state)
+        net.set_params(np.load(args.init_weights))
     t0 = time.time()
     val = _labelled(args, args.val_seed, args.val, t0, "validation", args.label_budget)
     data = _labelled(args, args.first_seed, args.graphs, t0, "training", args.label_budget)
@@ -125,6 +139,7 @@ def train(args):
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     total_steps = max(1, args.epochs * len(data))
     step = 0
+    skipped = 0
     best = float("inf")
     for ep in range(args.epochs):
         t_ep = time.time()
@@ -133,13 +148,19 @@ def train(args):
         for i in order:
             A, z, V = data[i]
             lr = args.lr * (0.05 + 0.95 * 0.5 * (1.0 + np.cos(np.pi * step / total_steps)))
-            loss, _ = net.backward(A, z, V)
+            step += 1
+            try:
+                loss, _ = net.backward(A, z, V)
+            except F.FeError as e:  # rank-deficient output on this graph: no step
+                if e.status != F.FE_EBREAKDOWN:
+                    raise
+                skipped += 1
+                continue
             if np.isfinite(loss):
                 net.adam(lr, clip=args.clip)
             losses.append(loss)
-            step += 1
         history.append(float(np.nanmean(losses)))
-        vl = float(np.mean([net.backward(A, z, V)[0] for A, z, V in val])) if val else history[-1]
+        vl = float(np.mean([val_loss(net, A, z, V) for A, z, V in val])) if val else history[-1]
         val_hist.append(vl)
         if vl < best:
             best = vl
@@ -153,7 +174,9 @@ def train(args):
     print(json.dumps({"train_loss": history, "val_loss": val_hist, "best_val_loss": best,
                       "graphs": len(data), "val_graphs": len(val), "epochs": len(history),
                       "label_s": t_label, "seconds": time.time() - t0, "lr": args.lr,
-                      "clip": args.clip, "compute": args.compute}), flush=True)
+                      "clip": args.clip, "compute": args.compute,
+                      "init_weights": args.init_weights, "skipped_steps": skipped}),
+          flush=True)
 
 
 def evaluate(weights, heldout, first_seed=3000, max_log2n=18, random_seeds=3, log=print):
@@ -230,6 +253,7 @@ def main():
     t.add_argument("--clip", type=float, default=1.0, help="global gradient-norm clip (0: off)")
     t.add_argument("--val", type=int, default=100, help="validation graphs")
     t.add_argument("--val-seed", type=int, default=9000)
+    t.add_argument("--init-weights", default=None, help="start from these weights")
     t.add_argument("--label-budget", type=float, default=300.0, help="seconds")
     t.add_argument("--time-budget", type=float, default=760.0, help="seconds, whole run")
     e = sub.add_parser("eval")

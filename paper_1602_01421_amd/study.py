@@ -148,11 +148,14 @@ def large(args):
 
 
 def large_config(F, A, args, nev, b, m):
+    """Solves of one shape.  With --seeds S: random starts from seeds 1..S and,
+    for every weights file, S draws of the network's random inputs."""
     from .learned import learned_start
     import torch
     _log(f"[study] configuration nev {nev}, block {b}, m {m}")
     mr = args.max_restarts
     runs = set(args.runs.split(","))
+    seeds = list(range(1, max(1, args.seeds) + 1))
     rows, ref_evals = [], None
     if "f64" in runs:
         ref_row, ref = run_solve(F, A, "f64_reference", nev=nev, block=b, m=m, tol=1e-10,
@@ -160,40 +163,46 @@ def large_config(F, A, args, nev, b, m):
         rows.append(ref_row)
         ref_evals = ref.evals
         torch.cuda.empty_cache()
-    if "f32" in runs:
-        rows.append(run_solve(F, A, "f32_random_start", ref_evals, nev=nev, block=b, m=m,
-                              tol=1e-6, dtype=torch.float32, seed=1, max_restarts=mr)[0])
-        torch.cuda.empty_cache()
-    if args.weights and b in (1, 2, 4, 8) and ("learned" in runs or "learned32" in runs):
-        net = F.Gnn(seed=0, compute="bf16")
-        net.set_params(np.load(args.weights))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g = torch.Generator(device="cuda")
-        g.manual_seed(args.scale)
-        z = torch.randn((A.n, 15), generator=g, device="cuda", dtype=torch.float32)
-        X = learned_start(net, A, z, torch.float32, block=b)
-        del z
-        net.close()  # releases the inference workspace (4 x n x 64 floats)
-        torch.cuda.synchronize()
-        t_inf = time.perf_counter() - t0
-        _log(f"[study] network inference {t_inf:.2f} s (fallback: {X is None})")
-        for tag, mixed in (("learned", True), ("learned32", False)):
-            if tag not in runs:
-                continue
-            row, _ = run_solve(F, A, "learned_start_" + ("mixed" if mixed else "f32"), ref_evals,
-                               nev=nev, block=b, m=m, tol=1e-6, dtype=torch.float32, seed=1,
-                               start=X, mixed=mixed, max_restarts=mr)
-            row["inference_s"] = t_inf
-            row["end_to_end_s"] = t_inf + row["seconds"]
-            row["fallback"] = X is None
+    for mixed, tag in ((False, "f32"), (True, "mixed")):
+        if tag not in runs:
+            continue
+        for sd in seeds:
+            row, _ = run_solve(F, A, "f32_random_start" if not mixed else "random_start_mixed",
+                               ref_evals, nev=nev, block=b, m=m, tol=1e-6, dtype=torch.float32,
+                               seed=sd, mixed=mixed, max_restarts=mr)
+            row["seed"] = sd
             rows.append(row)
-        del X
-        torch.cuda.empty_cache()
-    if "mixed" in runs:
-        rows.append(run_solve(F, A, "random_start_mixed", ref_evals, nev=nev, block=b, m=m,
-                              tol=1e-6, dtype=torch.float32, seed=1, mixed=True,
-                              max_restarts=mr)[0])
+            torch.cuda.empty_cache()
+    weights = [w for w in (args.weights or "").split(",") if w]
+    if b in (1, 2, 4, 8) and ("learned" in runs or "learned32" in runs):
+        for wi, wpath in enumerate(weights):
+            for sd in seeds:
+                net = F.Gnn(seed=0, compute="bf16")
+                net.set_params(np.load(wpath))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g = torch.Generator(device="cuda")
+                g.manual_seed(args.scale * 1000 + sd - 1 if sd > 1 else args.scale)
+                z = torch.randn((A.n, 15), generator=g, device="cuda", dtype=torch.float32)
+                X = learned_start(net, A, z, torch.float32, block=b)
+                del z
+                net.close()  # releases the inference workspace (4 x n x 64 floats)
+                torch.cuda.synchronize()
+                t_inf = time.perf_counter() - t0
+                _log(f"[study] network inference {t_inf:.2f} s (weights {wi}, draw {sd}, "
+                     f"fallback: {X is None})")
+                for tag, mixed in (("learned", True), ("learned32", False)):
+                    if tag not in runs:
+                        continue
+                    row, _ = run_solve(F, A, "learned_start_" + ("mixed" if mixed else "f32"),
+                                       ref_evals, nev=nev, block=b, m=m, tol=1e-6,
+                                       dtype=torch.float32, seed=1, start=X, mixed=mixed,
+                                       max_restarts=mr)
+                    row.update({"inference_s": t_inf, "end_to_end_s": t_inf + row["seconds"],
+                                "fallback": X is None, "weights": wpath, "draw": sd})
+                    rows.append(row)
+                del X
+                torch.cuda.empty_cache()
     return {"nev": nev, "block": b, "m": m, "max_restarts": mr, "solves": rows}
 
 
@@ -210,7 +219,9 @@ def main():
     q.add_argument("--configs", default="8x48",
                    help="comma list of BLOCKxM solve shapes, all nev 8 (e.g. 8x48,4x64)")
     q.add_argument("--max-restarts", type=int, default=500)
-    q.add_argument("--weights", default=None)
+    q.add_argument("--weights", default=None, help="comma list of learned-start weight files")
+    q.add_argument("--seeds", type=int, default=1,
+                   help="random starts 1..S and S draws of the network inputs per weights file")
     q.add_argument("--spmm-reps", type=int, default=10)
     q.add_argument("--runs", default="f64,f32,learned,learned32,mixed",
                    help="solves: f64 (reference), f32, learned (mixed storage), learned32, mixed")

@@ -5,7 +5,7 @@ generated graphs with seeds 1000..2999, validation 9000..9099) are run on
 held-out graphs of the same family (seeds from 3000): FP64 storage, nev 8,
 block 8, m 48, tol 1e-8, learned start vs the median of three random starts.
 Bars (set with margin under what the held-out evaluation measured, a median
-of 0.85 of the random products on Chung-Lu graphs): on the first 12 held-out
+of 0.84 of the random products on Chung-Lu graphs): on the first 12 held-out
 Chung-Lu graphs with n <= 2^16 the learned start needs no more products than
 the random median on at least 9, and at most 0.95 of their total; every
 learned solve converges and passes the solver's own FP64 residual check.
