@@ -189,7 +189,9 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path would "
-              f"shard by row blocks, see the design notes)", file=sys.stderr)
+              f"shard by row blocks: each GPU owning a row range of A, X and every subspace "
+              f"block, one all-gather of X per product and one all-reduce per Gram)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -50,7 +50,7 @@ typedef enum {
   FE_EDEVICE = 3,      /* a HIP runtime call failed; text in fe_last_error() */
   FE_ENOCONV = 4,      /* solver stopped at max_restarts; outputs hold best estimates */
   FE_EBREAKDOWN = 5,   /* subspace could not be extended (refill failed) */
-  FE_EUNSUPPORTED = 6  /* valid request this build does not implement */
+  FE_EUNSUPPORTED = 6  /* valid request outside the library's limits (sizes, shapes) */
 } fe_status;
 
 typedef enum { FE_F64 = 0, FE_F32 = 1, FE_BF16 = 2 } fe_dtype;
