@@ -206,3 +206,21 @@ def test_subspace_limits(fe):
         with pytest.raises(fe.FeError) as e:
             fe.fe_krylov_schur(A, *args, 1e-8, dtype=torch.float32)
         assert e.value.status == fe.FE_EUNSUPPORTED
+
+
+def test_start_block_with_nan_and_repeated_columns(fe):
+    """A caller's start block whose columns are not finite, or repeat, is
+    repaired by the block QR's refill (the solver still converges)."""
+    g = S.chung_lu_edges(20000, alpha=2.3, mean_deg=12, seed=9)
+    A, rp, ci = setup(fe, g)
+    ref = fe.fe_krylov_schur(A, 8, 4, 32, 1e-8, dtype=torch.float64, seed=3)
+    X0 = torch.tensor(S.normal((A.n, 4), seed=5), device="cuda")
+    X0[:, 2] = float("nan")
+    r = fe.fe_krylov_schur(A, 8, 4, 32, 1e-8, dtype=torch.float64, start=X0)
+    assert r.status == fe.FE_OK and r.refills >= 1
+    assert np.allclose(r.evals, ref.evals, rtol=1e-10)
+    X1 = torch.tensor(S.normal((A.n, 4), seed=6), device="cuda")
+    X1[:, 3] = X1[:, 1]
+    r = fe.fe_krylov_schur(A, 8, 4, 32, 1e-8, dtype=torch.float64, start=X1)
+    assert r.status == fe.FE_OK and r.refills >= 1
+    assert np.allclose(r.evals, ref.evals, rtol=1e-10)
