@@ -409,6 +409,17 @@ class Solver {
         for (int s2 = 0; s2 < na; ++s2) hM[acc[s1] * b + acc[s2]] = Rai[s1 * na + s2];
     }
     t_host += secs(th, clk::now());
+    if (!dep.empty()) {
+      // A dependent column may hold non-finite values (a caller's start block):
+      // overwrite it before the right multiplication, whose zero rows for it
+      // would still carry NaN through (NaN x 0).  The draws are counter-based,
+      // so the refill below writes the same values; for finite inputs the
+      // zero rows contribute exact zeros and nothing changes.
+      uint32_t mask = 0;
+      for (int j : dep) mask |= 1u << j;
+      FE_TRY(random_fill(W, n, b, mask, 1, o.seed, (uint32_t)step, A.relabeled ? A.d_perm : nullptr,
+                         dt, s));
+    }
     FE_TRY(right_mult(W));
     // Racc (na x na): accumulated second-stage factor of the accepted columns
     std::vector<double> Racc((size_t)na * na, 0.0);
