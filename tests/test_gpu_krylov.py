@@ -224,3 +224,20 @@ def test_start_block_with_nan_and_repeated_columns(fe):
     r = fe.fe_krylov_schur(A, 8, 4, 32, 1e-8, dtype=torch.float64, start=X1)
     assert r.status == fe.FE_OK and r.refills >= 1
     assert np.allclose(r.evals, ref.evals, rtol=1e-10)
+
+
+@pytest.mark.parametrize("nev,b,m", [(4, 1, 24), (6, 2, 32), (8, 16, 64)])
+def test_block_widths_fp64_match_oracle(fe, nev, b, m):
+    """Block widths 1, 2 (element-load Gram) and 16 (widest factor kernels):
+    FP64 storage, same start block as the oracle: same products, eigenvalues
+    within 1e-10."""
+    g = S.chung_lu_edges(30000, alpha=2.2, mean_deg=12, seed=17)
+    A, rp, ci = setup(fe, g)
+    X0 = S.normal((A.n, b), seed=8)
+    ref = oracle_ks(rp, ci, A.n, nev, b, m, 1e-9, X0)
+    r = fe.fe_krylov_schur(A, nev, b, m, 1e-9, dtype=torch.float64,
+                           start=torch.tensor(X0, device="cuda"))
+    assert r.status == fe.FE_OK and ref.converged
+    assert np.allclose(r.evals, ref.evals, rtol=1e-10, atol=0)
+    assert r.spmm_calls == ref.spmm_calls
+    check_vectors(rp, ci, r)
