@@ -224,9 +224,10 @@ typedef struct {
  * descending, ties to the larger theta); evecs (device n x nev in opts->dt,
  * original vertex order, 2-norm 1 up to storage rounding) or NULL; rep (host)
  * or NULL.
- * Workspace: (m + block) * n elements of dt, 2 * nev * n doubles and small
- * FP64 buffers, allocated for the call and freed before return.  Synchronises the
- * stream before returning.
+ * Workspace: (m + block) * n elements of dt (mixed: of BF16, then from the
+ * switch of dt, with n * block doubles during the switch), 2 * nev * n
+ * doubles and small FP64 buffers, allocated for the call and freed before
+ * return.  Synchronises the stream before returning.
  * Errors: FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_ENOCONV (max_restarts reached;
  * outputs hold the current estimates), FE_EUNSUPPORTED (sizes beyond the limits).
  */
@@ -235,14 +236,14 @@ fe_status fe_krylov_schur(const fe_csr *A, int32_t nev, int32_t block, int32_t m
                           fe_ks_report *rep);
 
 /* ------------------------------------------------------------------------
- * Learned start block (not in the paper; the learned warm start of this
- * build).  A three-layer graph network over Ahat = D^-1/2 A D^-1/2:
+ * Learned start block (not in the paper: a learned warm start for the
+ * solver).  A three-layer graph network over Ahat = D^-1/2 A D^-1/2:
  *   h0_i = [log(1 + deg_i), z_i (15 values)]
  *   S_l = Ahat H_{l-1};  H_l = relu(S_l W_l + H_{l-1} U_l + b_l)   (hidden 64)
  *   X = H_3 P                                                      (8 columns)
  * Parameters live on the device as FP32 masters (flattened in the order
  * W0 U0 b0 W1 U1 b1 W2 U2 b2 P, matrices row-major, 19,136 floats); the dense
- * transforms run on BF16 MFMA with FP32 accumulation, aggregation on fe_spmm
+ * transforms run on BF16 (or FP32) MFMA with FP32 accumulation, aggregation on fe_spmm
  * in FP32.  z, V and X are device FP32 blocks in the ORIGINAL vertex order
  * (the library permutes for relabelled handles).  Loss against eigenvectors
  * V (n x 8, orthonormal): L = 1 - ||V^T Q||_F^2 / 8 with Q an orthonormal
