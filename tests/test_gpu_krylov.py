@@ -49,6 +49,13 @@ def test_tiny_config_fp64_matches_oracle(fe):
     assert r.spmm_calls == ref.spmm_calls and r.restarts == ref.restarts
     assert r.resid.max() <= 1e-7
     check_vectors(rp, ci, r)
+    # eigenvector subspaces: largest principal angle between the GPU's and the
+    # oracle's 8-dimensional bases (|lambda_8| = 84.5 is well apart from
+    # |lambda_9| = 78.5, so the subspace is determined to ~ resid / gap)
+    Q1, _ = np.linalg.qr(r.evecs.cpu().numpy())
+    Q2, _ = np.linalg.qr(ref.evecs)
+    cos = np.linalg.svd(Q1.T @ Q2, compute_uv=False)
+    assert np.sqrt(max(0.0, 1.0 - cos.min() ** 2)) <= 1e-6
 
 
 CLOSED = {
