@@ -138,13 +138,15 @@ def learned_vs_random(P, A, stream, weights, tol, block, m, seeds=3):
     """
     import numpy as np
     import torch
-    from paper_1602_01421_amd.learned import learned_start
+    from paper_1602_01421_amd.learned import START_CHECK, START_DROP, learned_start
     net = P.Gnn(seed=0, compute="bf16")
     net.set_params(np.load(weights))
 
     def solve(start=None, seed=1):
         return P.fe_krylov_schur(A, 8, block, m, tol, dtype=torch.float32, start=start,
-                                 seed=seed, stream=stream, want_vectors=False)
+                                 seed=seed, stream=stream, want_vectors=False,
+                                 start_check=START_CHECK if start is not None else 0,
+                                 start_drop=START_DROP)
 
     solve(seed=99)  # warm-up at this block width
     rand = []
@@ -166,7 +168,8 @@ def learned_vs_random(P, A, stream, weights, tol, block, m, seeds=3):
         t_inf = time.perf_counter() - t0
         r = solve(start=X, seed=1 + k)
         torch.cuda.synchronize()
-        learned.append((time.perf_counter() - t0, r.spmm_calls, r.status, t_inf, X is None))
+        learned.append((time.perf_counter() - t0, r.spmm_calls, r.status, t_inf, X is None,
+                        r.start_fallback >= 0))
         del z, X
     net.close()
     med = lambda xs: float(np.median(xs))  # noqa: E731
@@ -176,6 +179,7 @@ def learned_vs_random(P, A, stream, weights, tol, block, m, seeds=3):
            "learned_spmm": med([x[1] for x in learned]),
            "inference_s": med([x[3] for x in learned]),
            "fallbacks": int(sum(x[4] for x in learned)),
+           "in_solve_fallbacks": int(sum(x[5] for x in learned)),
            "all_converged": all(x[2] == 0 for x in rand + learned)}
     res["time_ratio"] = res["learned_s"] / res["random_s"]
     res["spmm_ratio"] = res["learned_spmm"] / res["random_spmm"]

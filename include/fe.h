@@ -183,6 +183,16 @@ typedef struct {
                             vectors (column j: those with index = j mod block).
                             The caller's start block, if any, is rounded to BF16. */
   double mixed_switch;   /* 0 -> 1e-3 */
+  int32_t start_check;   /* with a caller's start block: 0 = keep it whatever happens;
+                            c > 0 = abandon it if the worst wanted residual estimate
+                            has not fallen start_drop-fold below its value at the first
+                            Rayleigh-Ritz step by the c-th restart.  The solve then
+                            starts again from the N(0,1) block of `seed` (the block
+                            and refill draws of a solve without a start block) in its
+                            current storage; the products spent so far stay counted.
+                            Ignored without a start block.  (A fallback rule for
+                            learned start blocks; not in the paper.) */
+  double start_drop;     /* 0 -> 10 */
 } fe_ks_opts;
 
 /* Per-solve report (all times in seconds). */
@@ -205,6 +215,8 @@ typedef struct {
                               kernel classes: SpMM 4 nnz + 8 (n+1) + 2 n b s; Gram n k s;
                               update n b s (k/b + 2) (s = element size) */
   double t_host, t_total;  /* host small-matrix work; wall clock of the solve */
+  int32_t start_fallback;  /* restart at which the caller's start block was abandoned
+                              (opts.start_check), -1 if never */
 } fe_ks_report;
 
 /*

@@ -520,6 +520,14 @@ class Solver {
     std::vector<double> theta(m), Y((size_t)m * m), rho(m);
     bool converged = false;
     int nconv = 0;
+    // Start-block check: the worst wanted estimate at the first Rayleigh-Ritz
+    // step is the reference; the caller's block is kept once an estimate falls
+    // start_drop-fold below it, and abandoned if none has by restart
+    // start_check.
+    bool start_watch = o.start != nullptr && o.start_check > 0;
+    const double start_drop = o.start_drop > 0 ? o.start_drop : 10.0;
+    double start_ref = 0.0;
+    int start_fallback = -1;
     struct Pending {
       int wb, step0;
     };
@@ -610,6 +618,31 @@ class Solver {
                 restarts, spmm_calls, nconv, nev, worst, theta[0]);
       }
       if (converged || restarts >= max_restarts) break;
+      if (start_watch) {
+        double worst = 0.0;
+        for (int j = 0; j < nev; ++j) worst = std::max(worst, rho[j]);
+        if (restarts == 0) {
+          start_ref = worst;
+        } else if (worst * start_drop <= start_ref) {
+          start_watch = false;
+        } else if (restarts >= o.start_check) {
+          // a fresh start from the seed's N(0,1) block; with the step count
+          // reset the refill draws are those of a solve without a start block
+          start_watch = false;
+          start_fallback = restarts;
+          prof.begin(P_OTHER);
+          FE_TRY(random_fill(blk(0), n, b, 0xFFFFFFFFu, 0, o.seed, 0, perm, dt, s));
+          prof.end();
+          worst_hist.clear();
+          std::fill(T.begin(), T.end(), 0.0);
+          std::fill(Bk.begin(), Bk.end(), 0.0);
+          step = 0;
+          FE_TRY(orth_block(0, C, R));
+          k = 0;
+          ++restarts;
+          continue;
+        }
+      }
       if (dt != dt_final) {  // mixed: widen once BF16 stalls or is good enough
         double worst = 0.0;
         for (int j = 0; j < nev; ++j) worst = std::max(worst, rho[j]);
@@ -699,6 +732,7 @@ class Solver {
       rep->update_calls = update_calls;
       rep->switch_restart = switch_restart;
       rep->spmm_calls_low = spmm_low;
+      rep->start_fallback = start_fallback;
       for (int j = 0; j < nev; ++j) {
         rep->rho[j] = rho[j];
         rep->ritz[j] = theta[j];

@@ -40,7 +40,8 @@ class KsOpts(ctypes.Structure):
                 ("start", ctypes.c_void_p), ("hip_stream", ctypes.c_void_p),
                 ("eta", ctypes.c_double), ("profile", ctypes.c_int32),
                 ("verbose", ctypes.c_int32), ("mixed", ctypes.c_int32),
-                ("mixed_switch", ctypes.c_double)]
+                ("mixed_switch", ctypes.c_double), ("start_check", ctypes.c_int32),
+                ("start_drop", ctypes.c_double)]
 
 
 class KsReport(ctypes.Structure):
@@ -55,7 +56,8 @@ class KsReport(ctypes.Structure):
                 ("t_update", ctypes.c_double), ("t_other_dev", ctypes.c_double),
                 ("bytes_spmm", ctypes.c_double), ("bytes_gram", ctypes.c_double),
                 ("bytes_update", ctypes.c_double),
-                ("t_host", ctypes.c_double), ("t_total", ctypes.c_double)]
+                ("t_host", ctypes.c_double), ("t_total", ctypes.c_double),
+                ("start_fallback", ctypes.c_int32)]
 
 
 _lib = None
@@ -286,13 +288,15 @@ class KsResult:
     bytes_update: float
     t_host: float
     t_total: float
+    start_fallback: int = -1
 
 
 def fe_krylov_schur(A: Csr, nev: int, block: int, m: int, tol: float, dtype=None, start=None,
                     seed: int = 0, max_restarts: int = 0, eta: float = 0.0, stream=None,
                     want_vectors: bool = True, profile: bool = False,
                     verbose: bool = False, mixed: bool = False,
-                    mixed_switch: float = 0.0) -> KsResult:
+                    mixed_switch: float = 0.0, start_check: int = 0,
+                    start_drop: float = 0.0) -> KsResult:
     """Block Krylov-Schur for the nev largest-magnitude eigenpairs (see fe.h)."""
     import torch
     if dtype is None:
@@ -308,6 +312,8 @@ def fe_krylov_schur(A: Csr, nev: int, block: int, m: int, tol: float, dtype=None
     o.verbose = int(verbose)
     o.mixed = int(mixed)
     o.mixed_switch = mixed_switch
+    o.start_check = start_check
+    o.start_drop = start_drop
     o.hip_stream = _stream(stream).value
     if start is not None:
         if start.shape != (A.n, block) or start.dtype != dtype:
@@ -329,7 +335,7 @@ def fe_krylov_schur(A: Csr, nev: int, block: int, m: int, tol: float, dtype=None
                     t_update=rep.t_update, t_other_dev=rep.t_other_dev,
                     bytes_spmm=rep.bytes_spmm, bytes_gram=rep.bytes_gram,
                     bytes_update=rep.bytes_update, t_host=rep.t_host,
-                    t_total=rep.t_total)
+                    t_total=rep.t_total, start_fallback=rep.start_fallback)
 
 
 def fe_dense_symeig(a: np.ndarray):

@@ -97,6 +97,7 @@ def run_solve(F, A, label, ref=None, **kw):
     row = {"run": label, "status": int(r.status), "seconds": t, "restarts": r.restarts,
            "spmm_calls": r.spmm_calls, "spmm_calls_bf16": r.spmm_calls_low,
            "switch_restart": r.switch_restart, "refills": r.refills,
+           "start_fallback": r.start_fallback,
            "max_resid": float(np.max(r.resid)), "evals": [float(x) for x in r.evals]}
     if ref is not None:
         row["max_eval_rel_err_vs_f64"] = float(np.max(np.abs(r.evals - ref) / np.abs(ref)))
@@ -150,7 +151,7 @@ def large(args):
 def large_config(F, A, args, nev, b, m):
     """Solves of one shape.  With --seeds S: random starts from seeds 1..S and,
     for every weights file, S draws of the network's random inputs."""
-    from .learned import learned_start
+    from .learned import START_CHECK, START_DROP, learned_start
     import torch
     _log(f"[study] configuration nev {nev}, block {b}, m {m}")
     mr = args.max_restarts
@@ -197,7 +198,9 @@ def large_config(F, A, args, nev, b, m):
                     row, _ = run_solve(F, A, "learned_start_" + ("mixed" if mixed else "f32"),
                                        ref_evals, nev=nev, block=b, m=m, tol=1e-6,
                                        dtype=torch.float32, seed=1, start=X, mixed=mixed,
-                                       max_restarts=mr)
+                                       max_restarts=mr,
+                                       start_check=START_CHECK if X is not None else 0,
+                                       start_drop=START_DROP)
                     row.update({"inference_s": t_inf, "end_to_end_s": t_inf + row["seconds"],
                                 "fallback": X is None, "weights": wpath, "draw": sd})
                     rows.append(row)

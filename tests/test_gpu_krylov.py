@@ -139,8 +139,9 @@ def test_no_convergence_and_bad_args(fe):
 
 
 def test_mixed_precision_bf16_to_fp32(fe):
-    """Storage starts in BF16 and is widened to FP32 in place of the Krylov
-    state; the solve still reaches tol 1e-6 and the FP64-oracle eigenvalues."""
+    """Storage starts in BF16, then the solve restarts in FP32 from the folded
+    wanted Ritz vectors; it still reaches tol 1e-6 and the FP64-oracle
+    eigenvalues."""
     g = S.rmat_edges(14, seed=14)
     A, rp, ci = setup(fe, g)
     ref = oracle_ks(rp, ci, A.n, 8, 8, 64, 1e-12, S.normal((A.n, 8), seed=3))
@@ -248,3 +249,53 @@ def test_block_widths_fp64_match_oracle(fe, nev, b, m):
     assert np.allclose(r.evals, ref.evals, rtol=1e-10, atol=0)
     assert r.spmm_calls == ref.spmm_calls
     check_vectors(rp, ci, r)
+
+
+def _start_check_graph(fe):
+    g = S.chung_lu_edges(16384, alpha=2.2, mean_deg=12, seed=21)
+    return setup(fe, g)
+
+
+def test_start_check_fallback_is_the_random_start_solve(fe):
+    """A start block abandoned at restart c (start_drop so large that it
+    always fires): the rest of the solve is the solve without a start block
+    from the same seed, bit for bit, after m/b + c (m - p)/b products spent
+    on the abandoned start; both agree with the FP64 oracle."""
+    A, rp, ci = _start_check_graph(fe)
+    nev, b, m = 8, 4, 32
+    ref = fe.fe_krylov_schur(A, nev, b, m, 1e-8, dtype=torch.float64, seed=7)
+    X0 = torch.tensor(S.normal((A.n, b), seed=3), device="cuda")
+    for c in (1, 3):
+        r = fe.fe_krylov_schur(A, nev, b, m, 1e-8, dtype=torch.float64, seed=7, start=X0,
+                               start_check=c, start_drop=1e300)
+        p = m - b * max(1, (m - nev) // (2 * b))
+        assert r.status == fe.FE_OK and r.start_fallback == c
+        assert r.spmm_calls == ref.spmm_calls + m // b + c * (m - p) // b
+        assert r.restarts == ref.restarts + c + 1
+        assert np.array_equal(r.evals, ref.evals)
+        assert torch.equal(r.evecs, ref.evecs)
+    orc = oracle_ks(rp, ci, A.n, nev, b, m, 1e-8, X0.cpu().numpy())
+    assert np.allclose(ref.evals, orc.evals, rtol=1e-10, atol=0)
+
+
+def test_start_check_kept_start_changes_nothing(fe):
+    """A start block whose estimates fall (start_drop 1: any decrease keeps
+    it): the watched solve is the unwatched one, bit for bit; without a start
+    block the option is ignored; a mixed solve may abandon its start too."""
+    A, rp, ci = _start_check_graph(fe)
+    X0 = torch.tensor(S.normal((A.n, 4), seed=3), device="cuda")
+    plain = fe.fe_krylov_schur(A, 8, 4, 32, 1e-8, dtype=torch.float64, seed=7, start=X0)
+    kept = fe.fe_krylov_schur(A, 8, 4, 32, 1e-8, dtype=torch.float64, seed=7, start=X0,
+                              start_check=3, start_drop=1.0)
+    assert kept.start_fallback == -1 and plain.start_fallback == -1
+    assert np.array_equal(kept.evals, plain.evals) and kept.spmm_calls == plain.spmm_calls
+    rnd = fe.fe_krylov_schur(A, 8, 4, 32, 1e-8, dtype=torch.float64, seed=7)
+    rnd2 = fe.fe_krylov_schur(A, 8, 4, 32, 1e-8, dtype=torch.float64, seed=7,
+                              start_check=3, start_drop=1e300)
+    assert rnd2.start_fallback == -1 and np.array_equal(rnd.evals, rnd2.evals)
+    X32 = X0.float()
+    mx = fe.fe_krylov_schur(A, 8, 4, 32, 1e-6, dtype=torch.float32, seed=7, start=X32,
+                            mixed=True, start_check=2, start_drop=1e300)
+    assert mx.status == fe.FE_OK and mx.start_fallback == 2
+    assert np.all(np.abs(mx.evals - rnd.evals) <= 1e-8 * np.abs(rnd.evals))
+    assert mx.resid.max() <= 1e-6

@@ -9,8 +9,12 @@ of 0.84 of the random products on Chung-Lu graphs): on the first 12 held-out
 Chung-Lu graphs with n <= 2^16 the learned start needs no more products than
 the random median on at least 9, and at most 0.95 of their total; every
 learned solve converges and passes the solver's own FP64 residual check.
-Plus the fallback: a network whose output is not finite or rank deficient
-yields no start block, and the solve then runs from a random start.
+The learned solves run with the in-solve fallback rule on (a start whose
+worst residual estimate has not fallen below its first value within three
+restarts is abandoned for the random start).
+Plus the fallback before the solve: a network whose output is not finite or
+rank deficient yields no start block, and the solve then runs from a random
+start.
 """
 import os
 
@@ -55,7 +59,8 @@ def test_learned_start_needs_fewer_products(fe):
         wins += r.spmm_calls <= med
         tot_l += r.spmm_calls
         tot_r += med
-        print(f"{desc}: learned {r.spmm_calls} products, random median {med:.0f}")
+        print(f"{desc}: learned {r.spmm_calls} products (fallback at restart "
+              f"{r.start_fallback}), random median {med:.0f}")
     assert wins >= 9, wins
     assert tot_l <= 0.95 * tot_r, (tot_l, tot_r)
 

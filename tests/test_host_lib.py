@@ -1,5 +1,6 @@
 """CPU-side checks of the library: it loads, exports every declared symbol,
 and its host-only pieces behave (no GPU calls)."""
+import ctypes
 import os
 import re
 
@@ -71,3 +72,31 @@ def test_csr_build_validates_before_touching_the_device(fe):
     with pytest.raises(fe.FeError) as e:  # row not strictly increasing
         fe.fe_csr_from_csr(3, np.array([0, 2, 2, 2]), np.array([2, 1], np.int32))
     assert e.value.status == fe.FE_EINVAL
+
+
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and offsetof of a struct declared in include/fe.h, from gcc."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    body = "\n".join(f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields)
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"fe.h\"\nint main(void) {\n"
+                   f'  printf("%zu\\n", sizeof({struct}));\n{body}\n  return 0;\n}}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+@pytest.mark.parametrize("cls,struct", [("KsOpts", "fe_ks_opts"), ("KsReport", "fe_ks_report")])
+def test_binding_structs_match_header(cls, struct, tmp_path):
+    """The ctypes mirrors of the option and report structs have the C layout."""
+    from paper_1602_01421_amd import fe as F
+    C = getattr(F, cls)
+    names = [f[0] for f in C._fields_]
+    size, offs = _c_layout(struct, names, tmp_path)
+    assert ctypes.sizeof(C) == size
+    assert [getattr(C, f).offset for f in names] == offs
