@@ -336,8 +336,10 @@ __global__ __launch_bounds__(256) void layer_bwd_kernel(const float* __restrict_
 // a long sum with cancellation, so it runs on FP32 MFMA
 // (v_mfma_f32_16x16x4f32: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
 // D[i][j] in register i % 4 of lane j + 16 (i / 4), measured on gfx950).
-// Each 32-row step is staged in LDS transposed (feature / column major) with
-// an odd row stride, so every operand read is a conflict-free 4-byte read.
+// Each 32-row step is read with 16-byte loads and staged in LDS transposed
+// (feature / column major, odd row stride, so every operand read is a
+// conflict-free 4-byte read).  Several workgroups per CU keep loads in
+// flight while others compute.
 template <int DIN>
 __global__ __launch_bounds__(256) void wgrad_kernel(const float* __restrict__ T,
                                                     const float* __restrict__ Hp,
@@ -348,6 +350,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const float* __restrict__ T,
                                                     float* __restrict__ partials) {
   constexpr int NF = 2 * DIN + 1, MT = (NF + 15) / 16, NFP = MT * 16;
   constexpr int RS = 32 + 1;
+  constexpr int D4 = DIN / 4, H4 = HID / 4;
   __shared__ float Fs[NFP * RS];
   __shared__ float Zs[HID * RS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -356,27 +359,57 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const float* __restrict__ T,
   f32x4 acc[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // constant feature rows: the ones column and the zero padding (rows past
+  // the interval have dZ = 0, so their ones contribute nothing)
+  for (int e = threadIdx.x; e < (NFP - 2 * DIN) * 32; e += blockDim.x) {
+    const int f = 2 * DIN + e / 32, rr = e % 32;
+    Fs[f * RS + rr] = f == 2 * DIN ? 1.0f : 0.0f;
+  }
   const int64_t rb = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t re = min(n, rb + rows_per_wg);
   for (int64_t r0 = rb; r0 < re; r0 += 32) {
     __syncthreads();
-    for (int e = threadIdx.x; e < 32 * NFP; e += blockDim.x) {
-      const int rr = e / NFP, f = e % NFP;
+    for (int e = threadIdx.x; e < 32 * D4; e += blockDim.x) {
+      const int rr = e / D4, f4 = e % D4;
       const int64_t row = r0 + rr;
-      float v = 0.f;
+      float4 t = make_float4(0.f, 0.f, 0.f, 0.f), h = t;
       if (row < re) {
-        if (f < DIN) v = dinv[row] * T[row * DIN + f];
-        else if (f < 2 * DIN) v = Hp[row * DIN + (f - DIN)];
-        else if (f == 2 * DIN) v = 1.0f;
+        const float dv = dinv[row];
+        t = *reinterpret_cast<const float4*>(T + row * DIN + 4 * f4);
+        h = *reinterpret_cast<const float4*>(Hp + row * DIN + 4 * f4);
+        t.x = dv * t.x;
+        t.y = dv * t.y;
+        t.z = dv * t.z;
+        t.w = dv * t.w;
       }
-      Fs[f * RS + rr] = v;
+      float* ft = Fs + (4 * f4) * RS + rr;
+      ft[0] = t.x;
+      ft[RS] = t.y;
+      ft[2 * RS] = t.z;
+      ft[3 * RS] = t.w;
+      float* fh = Fs + (DIN + 4 * f4) * RS + rr;
+      fh[0] = h.x;
+      fh[RS] = h.y;
+      fh[2 * RS] = h.z;
+      fh[3 * RS] = h.w;
     }
-    for (int e = threadIdx.x; e < 32 * HID; e += blockDim.x) {
-      const int rr = e / HID, c = e % HID;
+    for (int e = threadIdx.x; e < 32 * H4; e += blockDim.x) {
+      const int rr = e / H4, c4 = e % H4;
       const int64_t row = r0 + rr;
-      float v = 0.f;
-      if (row < re && H[row * HID + c] > 0.f) v = dH[row * HID + c];
-      Zs[c * RS + rr] = v;
+      float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (row < re) {
+        const float4 g = *reinterpret_cast<const float4*>(dH + row * HID + 4 * c4);
+        const float4 a = *reinterpret_cast<const float4*>(H + row * HID + 4 * c4);
+        z.x = a.x > 0.f ? g.x : 0.f;
+        z.y = a.y > 0.f ? g.y : 0.f;
+        z.z = a.z > 0.f ? g.z : 0.f;
+        z.w = a.w > 0.f ? g.w : 0.f;
+      }
+      float* zz = Zs + (4 * c4) * RS + rr;
+      zz[0] = z.x;
+      zz[RS] = z.y;
+      zz[2 * RS] = z.z;
+      zz[3 * RS] = z.w;
     }
     __syncthreads();
 #pragma unroll
@@ -408,31 +441,79 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const float* __restrict__ T,
   }
 }
 
-// dP = H3^T dX over a fixed row interval per workgroup (thread: feature k, two columns).
+// dP = H3^T dX over a fixed row interval per workgroup.  Lane k owns feature
+// k and all NOUT columns; wavefront w takes rows rb + w, rb + w + 4, ... with
+// four rows in flight, and the four wavefront sums are added in LDS in a
+// fixed order.
 __global__ __launch_bounds__(256) void pgrad_kernel(const float* __restrict__ H3,
                                                     const float* __restrict__ dX, int64_t n,
                                                     int64_t rows_per_wg,
                                                     float* __restrict__ partials) {
-  const int k = threadIdx.x & 63, jg = threadIdx.x >> 6;
+  static_assert(NOUT == 8, "two float4 per output row");
+  __shared__ float red[4][HID * NOUT];
+  const int k = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t rb = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t re = min(n, rb + rows_per_wg);
-  float a0 = 0.f, a1 = 0.f;
-  for (int64_t r = rb; r < re; ++r) {
-    const float h = H3[r * HID + k];
-    a0 = fmaf(h, dX[r * NOUT + 2 * jg], a0);
-    a1 = fmaf(h, dX[r * NOUT + 2 * jg + 1], a1);
+  float a[NOUT];
+#pragma unroll
+  for (int j = 0; j < NOUT; ++j) a[j] = 0.f;
+  int64_t r = rb + w;
+  for (; r + 12 < re; r += 16) {
+    float h[4];
+    float4 x0[4], x1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t rr = r + 4 * u;
+      h[u] = H3[rr * HID + k];
+      x0[u] = *reinterpret_cast<const float4*>(dX + rr * NOUT);
+      x1[u] = *reinterpret_cast<const float4*>(dX + rr * NOUT + 4);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[0] = fmaf(h[u], x0[u].x, a[0]);
+      a[1] = fmaf(h[u], x0[u].y, a[1]);
+      a[2] = fmaf(h[u], x0[u].z, a[2]);
+      a[3] = fmaf(h[u], x0[u].w, a[3]);
+      a[4] = fmaf(h[u], x1[u].x, a[4]);
+      a[5] = fmaf(h[u], x1[u].y, a[5]);
+      a[6] = fmaf(h[u], x1[u].z, a[6]);
+      a[7] = fmaf(h[u], x1[u].w, a[7]);
+    }
   }
-  partials[(int64_t)blockIdx.x * HID * NOUT + k * NOUT + 2 * jg] = a0;
-  partials[(int64_t)blockIdx.x * HID * NOUT + k * NOUT + 2 * jg + 1] = a1;
+  for (; r < re; r += 4) {
+    const float h = H3[r * HID + k];
+#pragma unroll
+    for (int j = 0; j < NOUT; ++j) a[j] = fmaf(h, dX[r * NOUT + j], a[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < NOUT; ++j) red[w][k * NOUT + j] = a[j];
+  __syncthreads();
+  for (int e = threadIdx.x; e < HID * NOUT; e += blockDim.x)
+    partials[(int64_t)blockIdx.x * HID * NOUT + e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
 }
 
-// out[e] = sum over sets x of partials[x][e], fixed order
-__global__ void sum_sets_kernel(const float* __restrict__ partials, int nsets, int len,
-                                float* __restrict__ out) {
+// Fixed-order sum of per-workgroup partials in two stages:
+// stage[g][e] = sum of partials[x][e] over the sets x of group g (kSetGroup
+// consecutive sets), then out[e] = sum over g of stage[g][e], both in FP64.
+constexpr int kSetGroup = 32;
+
+__global__ void sum_sets_stage_kernel(const float* __restrict__ partials, int nsets, int len,
+                                      double* __restrict__ stage) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  const int g = blockIdx.y;
+  const int x1 = min(nsets, (g + 1) * kSetGroup);
+  double s = 0.0;
+  for (int x = g * kSetGroup; x < x1; ++x) s += partials[(int64_t)x * len + e];
+  stage[(int64_t)g * len + e] = s;
+}
+
+__global__ void sum_stage_kernel(const double* __restrict__ stage, int ngroups, int len,
+                                 float* __restrict__ out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= len) return;
   double s = 0.0;
-  for (int x = 0; x < nsets; ++x) s += partials[(int64_t)x * len + e];
+  for (int g = 0; g < ngroups; ++g) s += stage[(int64_t)g * len + e];
   out[e] = (float)s;
 }
 
@@ -479,8 +560,10 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
   p[e] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
 }
 
+// Workgroups (partial-sum sets) of the row reductions: at least 256 rows
+// each, at most 1024 sets (four workgroups per CU at the largest sizes).
 int wgrad_sets(int64_t n) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(256, (n + 255) / 256));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256));
 }
 
 }  // namespace
@@ -824,10 +907,17 @@ fe_status fe_gnn_backward(fe_gnn* g, const fe_csr* A, const float* z, const floa
     FE_TRY(ws.get(&dHp, n * HID));
     const int ps = wgrad_sets(n);
     const int64_t prow = (n + ps - 1) / ps;
+    const int ngroups = (ps + kSetGroup - 1) / kSetGroup;
+    double* stage;
+    FE_TRY(ws.get(&stage, (size_t)ngroups * (2 * HID + 1) * HID));
+    auto sum_sets = [&](const float* part, int len, float* out) {
+      hipLaunchKernelGGL(sum_sets_stage_kernel, dim3((len + 255) / 256, ngroups), dim3(256), 0, s,
+                         part, ps, len, stage);
+      hipLaunchKernelGGL(sum_stage_kernel, grid1(len), dim3(256), 0, s, stage, ngroups, len, out);
+    };
     FE_TRY(ws.get(&pP, (size_t)ps * HID * NOUT));
     hipLaunchKernelGGL(pgrad_kernel, dim3(ps), dim3(256), 0, s, f.H[NLAYER], dX, n, prow, pP);
-    hipLaunchKernelGGL(sum_sets_kernel, grid1(HID * NOUT), dim3(256), 0, s, pP, ps, HID * NOUT,
-                       g->grads + o.P);
+    sum_sets(pP, HID * NOUT, g->grads + o.P);
     hipLaunchKernelGGL(out_bwd_kernel, grid1(n * HID), dim3(256), 0, s, dX, g->params + o.P, n, dH);
     FE_HIP(hipGetLastError());
     FE_TRY(ws.get(&wpart, (size_t)ps * (2 * HID + 1) * HID));
@@ -844,7 +934,7 @@ fe_status fe_gnn_backward(fe_gnn* g, const fe_csr* A, const float* z, const floa
       else
         hipLaunchKernelGGL((wgrad_kernel<HID>), dim3(ps), dim3(256), 0, s, f.T[l], f.H[l], f.dinv,
                            dH, f.H[l + 1], n, wrow, wpart);
-      hipLaunchKernelGGL(sum_sets_kernel, grid1(nf * HID), dim3(256), 0, s, wpart, ps, nf * HID, C);
+      sum_sets(wpart, nf * HID, C);
       hipLaunchKernelGGL(place_grads_kernel, grid1(nf * HID), dim3(256), 0, s, C, din,
                          g->grads + o.W[l], g->grads + o.U[l], g->grads + o.b[l]);
       FE_HIP(hipGetLastError());

@@ -16,10 +16,17 @@ large
     (network inference on the GPU included in its time; the network's random
     inputs drawn on the GPU) and an FP64-storage reference solve.
 
-Both print one JSON line; progress goes to stdout as the steps finish.
+gnn
+    The learned start network's calls at the largest training-graph size
+    (Chung-Lu, n = 2^18, Pareto 2.1, mean degree 32): inference (BF16 and
+    FP32 transforms), the training step (forward, loss, backward) and the
+    Adam step, each timed with HIP events over repeated calls.
+
+Each prints one JSON line; progress goes to stdout as the steps finish.
 
     python -m paper_1602_01421_amd.study precision --scale 24
     python -m paper_1602_01421_amd.study large --scale 27 --weights W.npy
+    python -m paper_1602_01421_amd.study gnn
 """
 from __future__ import annotations
 
@@ -209,6 +216,46 @@ def large_config(F, A, args, nev, b, m):
     return {"nev": nev, "block": b, "m": m, "max_restarts": mr, "solves": rows}
 
 
+def gnn(args):
+    from . import fe as F
+    import fe_synth as S
+    import torch
+    n = 1 << args.log2n
+    _, s, d = S.chung_lu_edges(n, alpha=2.1, mean_deg=args.mean_deg, seed=1)
+    A = F.fe_csr_build(n, s, d, F.FE_GRAPH_DEFAULT | F.FE_RELABEL_BY_DEGREE)
+    _log(f"[study] Chung-Lu n={A.n} nnz={A.nnz} max_deg={A.max_deg}")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    z = torch.randn((n, 15), generator=g, device="cuda", dtype=torch.float32)
+    V, _ = torch.linalg.qr(torch.randn((n, 8), generator=g, device="cuda", dtype=torch.float64))
+    V = V.float().contiguous()
+    st = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"study": "gnn", "n": A.n, "nnz": A.nnz, "params": int(F.lib().fe_gnn_param_count())}
+    for compute in ("bf16", "f32"):
+        net = F.Gnn(seed=0, compute=compute)
+        X = torch.empty((n, 8), device="cuda", dtype=torch.float32)
+        row = {"forward_ms": timed(lambda: net.forward(A, z, X=X), args.reps),
+               "train_step_ms": timed(lambda: net.backward(A, z, V), args.reps),
+               "adam_ms": timed(lambda: net.adam(1e-4, clip=1.0), args.reps)}
+        net.close()
+        out[compute] = row
+        _log(f"[study] gnn {compute}: forward {row['forward_ms']:.3f} ms, forward+loss+backward "
+             f"{row['train_step_ms']:.3f} ms, Adam {row['adam_ms']:.3f} ms")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -228,7 +275,11 @@ def main():
     q.add_argument("--spmm-reps", type=int, default=10)
     q.add_argument("--runs", default="f64,f32,learned,learned32,mixed",
                    help="solves: f64 (reference), f32, learned (mixed storage), learned32, mixed")
-    for sp in (p, q):
+    r = sub.add_parser("gnn")
+    r.add_argument("--log2n", type=int, default=18)
+    r.add_argument("--mean-deg", type=float, default=32.0)
+    r.add_argument("--reps", type=int, default=20)
+    for sp in (p, q, r):
         sp.add_argument("--verbose", action="store_true",
                         help="one line per restart from the solver (stderr)")
     args = ap.parse_args()
@@ -236,7 +287,7 @@ def main():
     VERBOSE = args.verbose
     import torch
     torch.cuda.set_device(0)
-    {"precision": precision, "large": large}[args.cmd](args)
+    {"precision": precision, "large": large, "gnn": gnn}[args.cmd](args)
 
 
 if __name__ == "__main__":

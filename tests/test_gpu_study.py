@@ -49,3 +49,11 @@ def test_large_driver_small_scale(fe, capsys):
                 assert r["max_eval_rel_err_vs_f64"] <= 1e-8, (cfg["block"], name)
         assert by["learned_start_f32"]["fallback"] is False
         assert by["learned_start_f32"]["end_to_end_s"] >= by["learned_start_f32"]["seconds"]
+
+
+def test_gnn_driver_small(fe, capsys):
+    from paper_1602_01421_amd import study
+    d = run(capsys, study.gnn, log2n=12, mean_deg=16.0, reps=2)
+    assert d["n"] == 4096 and d["params"] == 19136
+    for mode in ("bf16", "f32"):
+        assert all(d[mode][k] > 0 for k in ("forward_ms", "train_step_ms", "adam_ms"))
