@@ -49,10 +49,14 @@ def cosine(a, b):
     return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
 
 
-@pytest.mark.parametrize("compute", ["f32", "bf16"])
-@pytest.mark.parametrize("relabel", [False, True])
-def test_gradients_match_oracle(fe, relabel, compute):
-    A, rp, ci, z, V = case(fe, n=5000, seed=9, relabel=relabel)
+@pytest.mark.parametrize("compute,relabel,n", [("f32", False, 5000), ("f32", True, 5000),
+                                               ("bf16", False, 5000), ("bf16", True, 5000),
+                                               ("f32", True, 21111)])
+def test_gradients_match_oracle(fe, relabel, compute, n):
+    """n = 5000: 20 row intervals with a ragged last one; n = 21111: 83
+    intervals, so the fixed-order set sum runs over three groups, the last
+    one partial."""
+    A, rp, ci, z, V = case(fe, n=n, seed=9, relabel=relabel)
     net = fe.Gnn(seed=3, compute=compute)
     params = fe.gnn_unflatten(net.get_params())
     for l in range(3):  # non-zero biases exercise the bias path
