@@ -11,10 +11,13 @@ precision
 
 large
     R-MAT scale 27 (134M vertices, ~4.2e9 stored nonzeros, int64 offsets),
-    nev 8, block 8, m 48: the product alone at block 8 (FP32), the plain FP32
-    solve from a random start, the learned-start mixed-precision solve
-    (network inference on the GPU included in its time; the network's random
-    inputs drawn on the GPU) and an FP64-storage reference solve.
+    nev 8, for each solve shape in --configs (BLOCKxM, default 8x48): the
+    product alone at the block width (FP32, median and 10th/90th percentile
+    of --spmm-reps launches), an FP64-storage reference solve, the plain FP32
+    solve from random starts, learned-start solves in FP32 and mixed storage
+    (network inference on the GPU included in their end-to-end time; the
+    network's random inputs drawn on the GPU) and a mixed-storage solve from
+    a random start (--runs selects).
 
 gnn
     The learned start network's calls at the largest training-graph size
@@ -66,26 +69,34 @@ def build_rmat(F, scale: int):
 
 
 def time_spmm(F, A, b, dtype, reps=10):
-    """Mean duration (s) of one product at width b, HIP events on its stream."""
+    """One product at width b: 5 warm-up launches, then `reps` launches each
+    bracketed by HIP events on the product's stream; the median, 10th and
+    90th percentile durations (caches not flushed: X is gathered in steady
+    state)."""
     import torch
     g = torch.Generator(device="cuda")
     g.manual_seed(7)
     X = torch.randn((A.n, b), generator=g, device="cuda", dtype=torch.float32).to(dtype)
     Y = torch.empty_like(X)
     st = torch.cuda.Stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
     with torch.cuda.stream(st):
-        F.fe_spmm(A, X, Y, stream=st)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        for _ in range(reps):
+        for _ in range(5):
             F.fe_spmm(A, X, Y, stream=st)
-        e1.record(st)
+        for e0, e1 in ev:
+            e0.record(st)
+            F.fe_spmm(A, X, Y, stream=st)
+            e1.record(st)
     st.synchronize()
-    t = e0.elapsed_time(e1) / 1e3 / reps
+    ts = np.array([e0.elapsed_time(e1) / 1e3 for e0, e1 in ev])
+    t = float(np.median(ts))
     es = X.element_size()
     algo = 4.0 * A.nnz + 8.0 * (A.n + 1) + 2.0 * A.n * b * es
     del X, Y
     return {"b": b, "dtype": str(dtype).replace("torch.", ""), "ms": t * 1e3,
+            "ms_p10": float(np.percentile(ts, 10)) * 1e3,
+            "ms_p90": float(np.percentile(ts, 90)) * 1e3, "reps": reps,
             "gedge_col_s": A.nnz * b / t / 1e9, "gbs": algo / t / 1e9,
             "frac": algo / t / 1e9 / HBM_PEAK_GBS}
 
@@ -121,7 +132,8 @@ def precision(args):
     nev, b, m = 8, args.block, args.m
     out = {"study": "precision", "graph": f"rmat{args.scale}", "n": A.n, "nnz": A.nnz,
            "nev": nev, "block": b, "m": m, **info}
-    out["spmm"] = [time_spmm(F, A, b, torch.float32), time_spmm(F, A, b, torch.bfloat16)]
+    out["spmm"] = [time_spmm(F, A, b, torch.float32, reps=args.spmm_reps),
+                   time_spmm(F, A, b, torch.bfloat16, reps=args.spmm_reps)]
     _log(f"[study] product b={b}: " + ", ".join(f"{x['dtype']} {x['ms']:.2f} ms" for x in out["spmm"]))
     ref_row, ref = run_solve(F, A, "f64", nev=nev, block=b, m=m, tol=1e-10,
                              dtype=torch.float64, seed=1)
@@ -264,6 +276,7 @@ def main():
     p.add_argument("--block", type=int, default=8)
     p.add_argument("--m", type=int, default=64)
     p.add_argument("--bf16-restarts", type=int, default=200)
+    p.add_argument("--spmm-reps", type=int, default=50)
     q = sub.add_parser("large")
     q.add_argument("--scale", type=int, default=27)
     q.add_argument("--configs", default="8x48",

@@ -21,8 +21,10 @@ def run(capsys, fn, **kw):
 
 def test_precision_driver(fe, capsys):
     from paper_1602_01421_amd import study
-    d = run(capsys, study.precision, scale=12, block=8, m=64, bf16_restarts=200)
+    d = run(capsys, study.precision, scale=12, block=8, m=64, bf16_restarts=200, spmm_reps=5)
     assert d["n"] == 4096 and len(d["spmm"]) == 2
+    for x in d["spmm"]:
+        assert x["reps"] == 5 and x["ms_p10"] <= x["ms"] <= x["ms_p90"]
     by = {r["run"]: r for r in d["solves"]}
     assert set(by) == {"f64", "f32", "bf16", "mixed_bf16_f32"}
     assert by["f64"]["status"] == 0 and by["f64"]["max_resid"] <= 1e-9
