@@ -560,54 +560,84 @@ fe_status update_t(void* W, int64_t n, int32_t b, const void* V, int32_t nblk, i
 }
 
 // ------------------------------------------------------- rotate / combine
-// Out = V Y for V (n x m, m/B packed blocks) and Y (m x p, FP64): the restart
-// V[:, :p] <- V Y in place, or the packed FP64 Ritz vectors.  A dense
+// Out = beta Out + V (alpha Y) for V (n x m, m/B packed blocks) and Y (m x p,
+// FP64): the restart V[:, :p] <- V Y in place, the packed FP64 Ritz vectors,
+// and the solver's block updates W <- W - V C at wide blocks.  A dense
 // tall-and-skinny contraction, so it runs on v_mfma_f64_16x16x4f64 (lane
 // layouts measured on gfx950: A lane i + 16k, B lane j + 16k, D lane
-// j + 16 (i mod 4), register i / 4): a wavefront owns 16 rows, takes the m
-// columns four at a time (one V value per lane per step, Y from LDS, padded
-// to whole 16-column tiles with zeros) and stores only after the last step,
-// so every input of its rows is read before any output of them is written and
-// the in-place form is safe.  FP64 arithmetic for every storage type.
+// j + 16 (i mod 4), register i / 4): a wavefront owns 16 rows and stores only
+// after its last step, so every input of its rows is read before any output
+// of them is written and the in-place forms are safe.  When B is a multiple
+// of 4 the columns are taken sixteen at a time: lane (i, k) loads the four
+// consecutive columns 4k..4k+3 of its row with one vector load and feeds them
+// to four MFMA steps, step s contracting over columns {4k + s} (the B
+// operand, alpha Y from LDS padded with zeros to whole 16 x 16 tiles, is
+// indexed the same way).  Sixteen wavefronts per workgroup share the LDS copy
+// of Y.  FP64 arithmetic for every storage type.
 constexpr int kRotMax = 64;    // p (or c_out): at most four 16-column tiles
 constexpr int kRotRows = 128;  // largest m
+constexpr int kRotWG = 512;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <typename T, typename TO, int B>
-__global__ __launch_bounds__(256) void rotate_kernel(TO* Out, int32_t out_mode,  // may alias V
-                                                     int32_t c_out, int64_t n, const T* V,
-                                                     int32_t nblk,
-                                                     int64_t stride, const double* __restrict__ Y,
-                                                     int32_t p, int32_t p16) {
-  extern __shared__ double Ys[];  // m x p16
+template <typename T, typename TO, int B, int NT>
+__global__ __launch_bounds__(kRotWG) void rotate_kernel(TO* Out, int32_t out_mode,  // may alias V
+                                                        int32_t c_out, double beta, int64_t n,
+                                                        const T* V, int32_t nblk, int64_t stride,
+                                                        const double* __restrict__ Y, double alpha,
+                                                        int32_t p, int32_t p16, int32_t m16) {
+  extern __shared__ double Ys[];  // m16 x p16: alpha Y, zero beyond m and p
   const int m = nblk * B;
-  for (int i = threadIdx.x; i < m * p16; i += blockDim.x) {
+  for (int i = threadIdx.x; i < m16 * p16; i += blockDim.x) {
     const int t = i / p16, c = i - t * p16;
-    Ys[i] = c < p ? Y[t * p + c] : 0.0;
+    Ys[i] = (t < m && c < p) ? alpha * Y[t * p + c] : 0.0;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int ntile = p16 / 16;
+  const int nwave = blockDim.x >> 6;
   const int64_t ngroups = (n + 15) / 16;
-  for (int64_t g = (int64_t)blockIdx.x * 4 + wave; g < ngroups; g += (int64_t)gridDim.x * 4) {
+  for (int64_t g = (int64_t)blockIdx.x * nwave + wave; g < ngroups;
+       g += (int64_t)gridDim.x * nwave) {
     const int64_t r0 = g * 16;
     const int64_t ra = min(r0 + li, n - 1);  // this lane's A row (clamped; not stored)
-    f64x4 acc[kRotMax / 16];
+    f64x4 acc[NT];  // NT = p16 / 16 output tiles
 #pragma unroll
-    for (int t = 0; t < kRotMax / 16; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    if constexpr (B % 4 == 0) {
+      constexpr int VEC = 16 / sizeof(T) < 4 ? 16 / sizeof(T) : 4;
+      using A = typename Acc<T>::type;
+#pragma unroll 1
+      for (int kb = 0; kb < m; kb += 16) {
+        const int c0 = kb + 4 * lk;  // m is a multiple of 4: all four columns or none
+        const bool ok = c0 < m;
+        const int cc = ok ? c0 : 0;
+        const T* vp = V + (int64_t)(cc / B) * stride + ra * B + (cc % B);
+        A v[4];
+#pragma unroll
+        for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(vp + c, v + c);
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const double a = ok ? (double)v[st] : 0.0;
+          const double* yr = Ys + (c0 + st) * p16 + li;  // c0 + st < m16
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, yr[16 * t], acc[t], 0, 0, 0);
+        }
+      }
+    } else {
 #pragma unroll 4
-    for (int kb = 0; kb < m; kb += 4) {
-      const int col = kb + lk;
-      const double a = load_f64(V + (int64_t)(col / B) * stride + ra * B + (col % B));
-      const double* yr = Ys + col * p16 + li;
+      for (int kb = 0; kb < m; kb += 4) {
+        const int col = kb + lk;
+        const double a = col < m ? load_f64(V + (int64_t)(col / B) * stride + ra * B + (col % B)) : 0.0;
+        const double* yr = Ys + (col < m ? col : 0) * p16 + li;
 #pragma unroll
-      for (int t = 0; t < kRotMax / 16; ++t)
-        if (t < ntile) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, yr[16 * t], acc[t], 0, 0, 0);
+        for (int t = 0; t < NT; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, yr[16 * t], acc[t], 0, 0, 0);
+      }
     }
 #pragma unroll
-    for (int t = 0; t < kRotMax / 16; ++t) {
-      if (t < ntile) {
+    for (int t = 0; t < NT; ++t) {
+      {
         const int c = 16 * t + li;
 #pragma unroll
         for (int reg = 0; reg < 4; ++reg) {
@@ -616,7 +646,9 @@ __global__ __launch_bounds__(256) void rotate_kernel(TO* Out, int32_t out_mode, 
             if (out_mode == 0) {
               if (c < p) Out[(int64_t)(c / B) * stride + row * B + (c % B)] = to_storage<TO, double>(acc[t][reg]);
             } else if (c < c_out) {
-              Out[row * c_out + c] = to_storage<TO, double>(acc[t][reg]);
+              TO* o = Out + row * c_out + c;
+              const double x = beta != 0.0 ? fma(beta, load_f64(o), acc[t][reg]) : acc[t][reg];
+              *o = to_storage<TO, double>(x);
             }
           }
         }
@@ -626,32 +658,33 @@ __global__ __launch_bounds__(256) void rotate_kernel(TO* Out, int32_t out_mode, 
 }
 
 template <typename T, typename TO = T>
-fe_status rotate_t(void* Out, int32_t out_mode, int32_t c_out, int64_t n, int32_t b,
-                   const void* V, int32_t nblk, int64_t stride, const double* Y, int32_t p,
-                   hipStream_t s) {
+fe_status rotate_t(void* Out, int32_t out_mode, int32_t c_out, double beta, int64_t n, int32_t b,
+                   const void* V, int32_t nblk, int64_t stride, const double* Y, double alpha,
+                   int32_t p, hipStream_t s) {
   const int m = nblk * b;
   const int p16 = (p + 15) / 16 * 16;
-  const size_t lds = (size_t)m * p16 * sizeof(double);
+  const int m16 = (m + 15) / 16 * 16;
+  const size_t lds = (size_t)m16 * p16 * sizeof(double);
   if (p > kRotMax || m > kRotRows || lds > 64 * 1024)
     return fail(FE_EUNSUPPORTED, "rotate: m=%d (max %d), p=%d (max %d) or m*p too large", m,
                 kRotRows, p, kRotMax);
   const int64_t groups = (n + 15) / 16;
-  const uint32_t grid = (uint32_t)std::max<int64_t>(1, std::min<int64_t>((groups + 3) / 4, 8192));
+  const int wpg = kRotWG / 64;
+  const uint32_t grid = (uint32_t)std::max<int64_t>(1, std::min<int64_t>((groups + wpg - 1) / wpg, 2048));
   TO* O = static_cast<TO*>(Out);
   const T* Vp = static_cast<const T*>(V);
-#define FE_ROT(BB)                                                                               \
-  case BB:                                                                                       \
-    hipLaunchKernelGGL((rotate_kernel<T, TO, BB>), dim3(grid), dim3(256), lds, s, O, out_mode,   \
-                       c_out, n, Vp, nblk, stride, Y, p, p16);                                  \
-    break;
-  switch (b) {
-    FE_ROT(1) FE_ROT(2) FE_ROT(4) FE_ROT(8) FE_ROT(16)
-    default:
-      return fail(FE_EUNSUPPORTED, "rotate: block %d not in {1,2,4,8,16}", b);
+#define FE_ROT(BB, NTT)                                                                          \
+  if (b == BB && p16 == 16 * NTT) {                                                              \
+    hipLaunchKernelGGL((rotate_kernel<T, TO, BB, NTT>), dim3(grid), dim3(kRotWG), lds, s, O,     \
+                       out_mode, c_out, beta, n, Vp, nblk, stride, Y, alpha, p, p16, m16);      \
+    FE_HIP(hipGetLastError());                                                                   \
+    return FE_OK;                                                                                \
   }
+#define FE_ROT_B(BB) FE_ROT(BB, 1) FE_ROT(BB, 2) FE_ROT(BB, 3) FE_ROT(BB, 4)
+  FE_ROT_B(1) FE_ROT_B(2) FE_ROT_B(4) FE_ROT_B(8) FE_ROT_B(16)
+#undef FE_ROT_B
 #undef FE_ROT
-  FE_HIP(hipGetLastError());
-  return FE_OK;
+  return fail(FE_EUNSUPPORTED, "rotate: block %d not in {1,2,4,8,16}", b);
 }
 
 // -------------------------------------------------------------- residual
@@ -835,9 +868,9 @@ fe_status rotate_launch(void* V, int64_t n, int32_t b, int32_t nblk_in, int32_t 
                         int64_t stride, const double* Y, fe_dtype dt, hipStream_t s) {
   const int32_t p = nblk_out * b;
   switch (dt) {
-    case FE_F64: return rotate_t<double>(V, 0, 0, n, b, V, nblk_in, stride, Y, p, s);
-    case FE_F32: return rotate_t<float>(V, 0, 0, n, b, V, nblk_in, stride, Y, p, s);
-    case FE_BF16: return rotate_t<bf16_t>(V, 0, 0, n, b, V, nblk_in, stride, Y, p, s);
+    case FE_F64: return rotate_t<double>(V, 0, 0, 0.0, n, b, V, nblk_in, stride, Y, 1.0, p, s);
+    case FE_F32: return rotate_t<float>(V, 0, 0, 0.0, n, b, V, nblk_in, stride, Y, 1.0, p, s);
+    case FE_BF16: return rotate_t<bf16_t>(V, 0, 0, 0.0, n, b, V, nblk_in, stride, Y, 1.0, p, s);
   }
   return fail(FE_EINVAL, "rotate: bad dtype");
 }
@@ -845,11 +878,22 @@ fe_status rotate_launch(void* V, int64_t n, int32_t b, int32_t nblk_in, int32_t 
 fe_status combine_launch(double* Out, int32_t c, int64_t n, int32_t b, const void* V, int32_t nblk,
                          int64_t stride, const double* Y, fe_dtype dt, hipStream_t s) {
   switch (dt) {
-    case FE_F64: return rotate_t<double, double>(Out, 1, c, n, b, V, nblk, stride, Y, c, s);
-    case FE_F32: return rotate_t<float, double>(Out, 1, c, n, b, V, nblk, stride, Y, c, s);
-    case FE_BF16: return rotate_t<bf16_t, double>(Out, 1, c, n, b, V, nblk, stride, Y, c, s);
+    case FE_F64: return rotate_t<double, double>(Out, 1, c, 0.0, n, b, V, nblk, stride, Y, 1.0, c, s);
+    case FE_F32: return rotate_t<float, double>(Out, 1, c, 0.0, n, b, V, nblk, stride, Y, 1.0, c, s);
+    case FE_BF16: return rotate_t<bf16_t, double>(Out, 1, c, 0.0, n, b, V, nblk, stride, Y, 1.0, c, s);
   }
   return fail(FE_EINVAL, "combine: bad dtype");
+}
+
+fe_status mult_update_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk,
+                             int64_t stride, const double* C, double alpha, double beta,
+                             fe_dtype dt, hipStream_t s) {
+  switch (dt) {
+    case FE_F64: return rotate_t<double>(W, 1, b, beta, n, b, V, nblk, stride, C, alpha, b, s);
+    case FE_F32: return rotate_t<float>(W, 1, b, beta, n, b, V, nblk, stride, C, alpha, b, s);
+    case FE_BF16: return rotate_t<bf16_t>(W, 1, b, beta, n, b, V, nblk, stride, C, alpha, b, s);
+  }
+  return fail(FE_EINVAL, "update: bad dtype");
 }
 
 // ------------------------------------------- block QR factors on the device

@@ -102,6 +102,12 @@ fe_status update_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nb
 // V[:, 0:p] <- V[:, 0:m] * Y[:, 0:p] in place (Y: device FP64, m x p row-major)
 fe_status rotate_launch(void* V, int64_t n, int32_t b, int32_t nblk_in, int32_t nblk_out,
                         int64_t blk_stride, const double* Y, fe_dtype dt, hipStream_t s);
+// W <- beta W + alpha V[:, 0:k] C on the MFMA contraction of the restart
+// (C: device FP64, k x b row-major; W (n x b) may be V's own single block).
+// Same result as update_launch up to the order of the FP64 sums.
+fe_status mult_update_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk,
+                             int64_t blk_stride, const double* C, double alpha, double beta,
+                             fe_dtype dt, hipStream_t s);
 // Out (n x c packed, FP64) <- V[:, 0:m] * Y (m x c), V as blocks in dt.
 fe_status combine_launch(double* Out, int32_t c, int64_t n, int32_t b, const void* V, int32_t nblk,
                          int64_t blk_stride, const double* Y, fe_dtype dt, hipStream_t s);

@@ -264,9 +264,12 @@ class Solver {
     bytes[P_GRAM] += (double)n * nblk * b * es;  // W is the last of the nblk blocks
     return st;
   }
+  // Wide blocks (b >= 8) go to the MFMA contraction: the one-thread-per-row
+  // kernel's 2 k b FP64 FMAs per row make it VALU bound there.
   fe_status update(void* W, const void* Vp, int nblk, const double* C, double alpha, double beta) {
     prof.begin(P_UPDATE);
-    fe_status st = update_launch(W, n, b, Vp, nblk, stride, C, alpha, beta, dt, s);
+    fe_status st = b >= 8 ? mult_update_launch(W, n, b, Vp, nblk, stride, C, alpha, beta, dt, s)
+                          : update_launch(W, n, b, Vp, nblk, stride, C, alpha, beta, dt, s);
     prof.end();
     ++update_calls;
     const bool in_place = (W == Vp);

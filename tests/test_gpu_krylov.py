@@ -116,7 +116,8 @@ def test_rmat_bf16_storage(fe):
     ref = oracle_ks(rp, ci, A.n, 8, 8, 64, 1e-12, S.normal((A.n, 8), seed=3))
     r = fe.fe_krylov_schur(A, 8, 8, 64, 1e-2, dtype=torch.bfloat16, seed=5, max_restarts=200)
     assert r.status in (fe.FE_OK, fe.FE_ENOCONV)
-    assert np.all(np.abs(r.evals - ref.evals) <= 1e-3 * np.abs(ref.evals))
+    assert np.all(np.abs(r.evals - ref.evals) <= 1e-3 * np.abs(ref.evals)), (
+        r.status, r.restarts, r.evals, ref.evals, r.rho)
 
 
 def test_random_start_deterministic(fe):
@@ -204,6 +205,22 @@ def test_subspace_beyond_64_fp64_matches_oracle(fe):
     assert r.status == fe.FE_OK and ref.converged
     assert np.allclose(r.evals, ref.evals, rtol=1e-10, atol=0)
     assert r.spmm_calls == ref.spmm_calls
+    check_vectors(rp, ci, r)
+
+
+def test_wide_block_large_subspace_fp32(fe):
+    """Block 16, m 112 (the fastest shape on the scale-27 graph): block
+    updates and the restart run on the MFMA contraction with 16-column
+    groups; FP32 storage against the FP64 oracle run with the same shape."""
+    g = S.rmat_edges(14, seed=14)
+    A, rp, ci = setup(fe, g)
+    X0 = S.normal((A.n, 16), seed=5)
+    ref = oracle_ks(rp, ci, A.n, 8, 16, 112, 1e-12, X0)
+    r = fe.fe_krylov_schur(A, 8, 16, 112, 1e-6, dtype=torch.float32,
+                           start=torch.tensor(X0, dtype=torch.float32, device="cuda"))
+    assert r.status == fe.FE_OK
+    assert np.all(np.abs(r.evals - ref.evals) <= 1e-8 * np.abs(ref.evals))
+    assert r.resid.max() <= 1e-6
     check_vectors(rp, ci, r)
 
 
