@@ -32,6 +32,7 @@ namespace {
 constexpr int kGramWG = 512;          // 8 wavefronts
 constexpr int kGramRowsPerIter = 16;  // rows per wavefront per iteration (4 MFMA steps)
 constexpr int kGramPG = 4;            // 16-column V groups per workgroup (64 V columns)
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename T, int NQG>
 __global__ __launch_bounds__(kGramWG) void gram_kernel(const T* __restrict__ V, int64_t stride,
@@ -284,6 +285,82 @@ __global__ __launch_bounds__(1024) void reduce_partials(const double* __restrict
   }
 }
 
+// Same contraction for b = 16 on v_mfma_f64_16x16x4f64 (A lane i + 16k,
+// B lane j + 16k, D lane j + 16 (i mod 4), register i / 4): the output tile is
+// 16 V columns x 16 W columns and the contraction runs over rows, four per
+// step.  Lane (i, k) of step s reads column i of row r0 + 4k + s, so the 16
+// lanes of each quarter-wave read 16 consecutive columns of one row: no
+// transposes and no idle MFMA lanes.  (At b = 8 half of each tile would be
+// padding; the quad-transpose kernel is faster there.)  NPG 16-column V tiles
+// per workgroup slice;
+// tiles past k are fed zeros (their MFMAs are not skipped, which keeps every
+// accumulator chain unconditional).
+template <typename T, int NPG>
+__global__ __launch_bounds__(kGramWG) void gram16_kernel(const T* __restrict__ V, int64_t stride,
+                                                         const T* __restrict__ W, int64_t n,
+                                                         int32_t b, int32_t k,
+                                                         int64_t rows_per_wg,
+                                                         double* __restrict__ partials) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int p_base = blockIdx.y * (16 * kGramPG);
+  int64_t aoff[NPG];
+  bool aval[NPG];
+#pragma unroll
+  for (int pg = 0; pg < NPG; ++pg) {
+    const int c = p_base + 16 * pg + li;
+    aval[pg] = c < k;
+    aoff[pg] = aval[pg] ? (int64_t)(c / b) * stride + (c % b) : 0;
+  }
+  const bool bval = li < b;
+  const int lq = bval ? li : 0;
+  f64x4 acc[NPG];
+#pragma unroll
+  for (int pg = 0; pg < NPG; ++pg) acc[pg] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r_end = min(n, r_begin + rows_per_wg);
+  for (int64_t r0 = r_begin + wave * kGramRowsPerIter; r0 < r_end;
+       r0 += (kGramWG / 64) * kGramRowsPerIter) {
+    // unconditional loads from clamped addresses, masked afterwards
+    double bw[4], a[4][NPG];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int64_t row = r0 + 4 * lk + st;
+      const bool rv = row < r_end;
+      const int64_t rb = (rv ? row : r_end - 1) * b;
+      const double w = load_f64(W + rb + lq);
+      bw[st] = (rv && bval) ? w : 0.0;
+#pragma unroll
+      for (int pg = 0; pg < NPG; ++pg) {
+        const double x = load_f64(V + aoff[pg] + rb);
+        a[st][pg] = (rv && aval[pg]) ? x : 0.0;
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int pg = 0; pg < NPG; ++pg)
+        acc[pg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][pg], bw[st], acc[pg], 0, 0, 0);
+  }
+  // wavefront partials added in wavefront order (deterministic)
+  __shared__ double red[NPG][4][64];
+  for (int w = 0; w < kGramWG / 64; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int pg = 0; pg < NPG; ++pg)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[pg][r][lane] = (w == 0 ? 0.0 : red[pg][r][lane]) + acc[pg][r];
+    }
+    __syncthreads();
+  }
+  double* out = partials + (int64_t)blockIdx.x * k * b;
+  for (int idx = threadIdx.x; idx < NPG * 4 * 64; idx += kGramWG) {
+    const int l = idx & 63, r = (idx >> 6) & 3, pg = idx >> 8;
+    const int p = p_base + 16 * pg + 4 * r + (l >> 4), q = l & 15;
+    if (p < k && q < b) out[(int64_t)p * b + q] = red[pg][r][l];
+  }
+}
+
 int gram_sets(int64_t n) {
   // ~2 workgroups of 8 wavefronts per CU; never fewer rows than one iteration
   int64_t by_rows = (n + 8 * kGramRowsPerIter - 1) / (8 * kGramRowsPerIter);
@@ -305,10 +382,16 @@ fe_status gram_t(const void* V, int32_t nblk, int64_t stride, const void* W, int
 #define FE_GRAM(KERNEL, Q)                                                                    \
   hipLaunchKernelGGL((KERNEL<T, Q>), grid, dim3(kGramWG), 0, s, Vp, stride, Wp, n, b, k,      \
                      rows_per_wg, partials)
-  if (b % 4 == 0) {  // every 4-column group lies inside one block: 16-byte row loads
+  if (b == 16) {  // whole 16 x 16 MFMA tiles; zero V tiles past k
+    const int npg = std::min(kGramPG, (k + 15) / 16);
+    if (npg == 1) FE_GRAM(gram16_kernel, 1);
+    else if (npg == 2) FE_GRAM(gram16_kernel, 2);
+    else if (npg == 3) FE_GRAM(gram16_kernel, 3);
+    else FE_GRAM(gram16_kernel, 4);
+  } else if (b % 4 == 0) {  // 16-byte row loads and quad transposes
     if (b == 4) FE_GRAM(gram_wide_kernel, 1);
     else if (b == 8) FE_GRAM(gram_wide_kernel, 2);
-    else FE_GRAM(gram_wide_kernel, 4);
+    else FE_GRAM(gram_wide_kernel, 4);  // 16 W columns per z-slice
   } else if (b <= 4) {
     FE_GRAM(gram_kernel, 1);
   } else if (b <= 8) {
@@ -577,7 +660,6 @@ fe_status update_t(void* W, int64_t n, int32_t b, const void* V, int32_t nblk, i
 constexpr int kRotMax = 64;    // p (or c_out): at most four 16-column tiles
 constexpr int kRotRows = 128;  // largest m
 constexpr int kRotWG = 512;
-typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename T, typename TO, int B, int NT>
 __global__ __launch_bounds__(kRotWG) void rotate_kernel(TO* Out, int32_t out_mode,  // may alias V

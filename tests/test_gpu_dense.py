@@ -28,7 +28,8 @@ def host(t):
 
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("n,nblk,b", [(1, 1, 1), (37, 3, 4), (1000, 13, 4), (4097, 6, 8),
-                                      (777, 2, 16), (5000, 5, 3), (300, 1, 64), (70001, 12, 4)])
+                                      (777, 2, 16), (5000, 5, 3), (300, 1, 64), (70001, 12, 4),
+                                      (1001, 5, 16), (3333, 9, 8), (15, 8, 16)])
 def test_gram_small_int_bitwise(fe, dt, n, nblk, b):
     V = S.small_ints((nblk, n, b), seed=1, lo=-4, hi=4)
     W = S.small_ints((n, b), seed=2, lo=-4, hi=4)
@@ -38,7 +39,8 @@ def test_gram_small_int_bitwise(fe, dt, n, nblk, b):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("n,nblk,b", [(4099, 13, 4), (100003, 7, 8), (5000, 3, 16), (2000, 20, 2)])
+@pytest.mark.parametrize("n,nblk,b", [(4099, 13, 4), (100003, 7, 8), (5000, 3, 16), (2000, 20, 2),
+                                      (20011, 8, 16), (9999, 15, 8)])
 def test_gram_normal(fe, dt, n, nblk, b):
     Vd = dev(S.normal((nblk, n, b), seed=3), DT[dt])
     Wd = dev(S.normal((n, b), seed=4), DT[dt])
