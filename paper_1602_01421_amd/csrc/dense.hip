@@ -164,7 +164,7 @@ __device__ __forceinline__ void quad_transpose(A (&v)[4], int x) {
   }
 }
 
-template <typename T, int NQG>
+template <typename T, int NQG, int NPG>
 __global__ __launch_bounds__(kGramWG) void gram_wide_kernel(const T* __restrict__ V,
                                                             int64_t stride,
                                                             const T* __restrict__ W, int64_t n,
@@ -177,13 +177,12 @@ __global__ __launch_bounds__(kGramWG) void gram_wide_kernel(const T* __restrict_
   const int kk = lane >> 4, blk = (lane >> 2) & 3, x = lane & 3;
   const int p_base = blockIdx.y * (16 * kGramPG);
   const int q_base = blockIdx.z * (4 * NQG);
-  const int npg = min(kGramPG, (k - p_base + 15) / 16);
   const int nqg = min(NQG, (b - q_base + 3) / 4);
   // column group of this lane's quad: 4 consecutive columns inside one block
-  int64_t aoff[kGramPG];
-  bool aval[kGramPG];
+  int64_t aoff[NPG];
+  bool aval[NPG];
 #pragma unroll
-  for (int pg = 0; pg < kGramPG; ++pg) {
+  for (int pg = 0; pg < NPG; ++pg) {
     const int c0 = p_base + pg * 16 + 4 * blk;
     aval[pg] = c0 < k;
     aoff[pg] = aval[pg] ? (int64_t)(c0 / b) * stride + (c0 % b) : 0;
@@ -196,9 +195,9 @@ __global__ __launch_bounds__(kGramWG) void gram_wide_kernel(const T* __restrict_
     bval[qg] = q0 < b;
     boff[qg] = bval[qg] ? q0 : 0;
   }
-  double acc[kGramPG][NQG];
+  double acc[NPG][NQG];
 #pragma unroll
-  for (int pg = 0; pg < kGramPG; ++pg)
+  for (int pg = 0; pg < NPG; ++pg)
 #pragma unroll
     for (int qg = 0; qg < NQG; ++qg) acc[pg][qg] = 0.0;
 
@@ -209,9 +208,9 @@ __global__ __launch_bounds__(kGramWG) void gram_wide_kernel(const T* __restrict_
     const int64_t row = r0 + 4 * x + kk;  // the row this lane loads
     const bool rv = row < r_end;
     const int64_t rb = (rv ? row : r_end - 1) * b;
-    double a[4][kGramPG], bb[4][NQG];
+    double a[4][NPG], bb[4][NQG];
 #pragma unroll
-    for (int pg = 0; pg < kGramPG; ++pg) {
+    for (int pg = 0; pg < NPG; ++pg) {
       A v[4];
 #pragma unroll
       for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(V + aoff[pg] + rb + c, v + c);
@@ -237,19 +236,18 @@ __global__ __launch_bounds__(kGramWG) void gram_wide_kernel(const T* __restrict_
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int pg = 0; pg < kGramPG; ++pg)
-        if (pg < npg)
+      for (int pg = 0; pg < NPG; ++pg)
 #pragma unroll
           for (int qg = 0; qg < NQG; ++qg)
             if (qg < nqg)
               acc[pg][qg] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u][pg], bb[u][qg], acc[pg][qg],
                                                                0, 0, 0);
   }
-  __shared__ double red[kGramPG][NQG][64];
+  __shared__ double red[NPG][NQG][64];
   for (int w = 0; w < kGramWG / 64; ++w) {
     if (wave == w) {
 #pragma unroll
-      for (int pg = 0; pg < kGramPG; ++pg)
+      for (int pg = 0; pg < NPG; ++pg)
 #pragma unroll
         for (int qg = 0; qg < NQG; ++qg)
           red[pg][qg][lane] = (w == 0 ? 0.0 : red[pg][qg][lane]) + acc[pg][qg];
@@ -257,7 +255,7 @@ __global__ __launch_bounds__(kGramWG) void gram_wide_kernel(const T* __restrict_
     __syncthreads();
   }
   double* out = partials + (int64_t)blockIdx.x * k * b;
-  for (int idx = threadIdx.x; idx < kGramPG * NQG * 64; idx += kGramWG) {
+  for (int idx = threadIdx.x; idx < NPG * NQG * 64; idx += kGramWG) {
     const int l = idx & 63, qg = (idx >> 6) % NQG, pg = (idx >> 6) / NQG;
     const int i = l >> 4, bl = (l >> 2) & 3, j = l & 3;
     const int p = p_base + pg * 16 + 4 * bl + i, q = q_base + qg * 4 + j;
@@ -382,6 +380,9 @@ fe_status gram_t(const void* V, int32_t nblk, int64_t stride, const void* W, int
 #define FE_GRAM(KERNEL, Q)                                                                    \
   hipLaunchKernelGGL((KERNEL<T, Q>), grid, dim3(kGramWG), 0, s, Vp, stride, Wp, n, b, k,      \
                      rows_per_wg, partials)
+#define FE_GRAM2(KERNEL, Q, P)                                                                \
+  hipLaunchKernelGGL((KERNEL<T, Q, P>), grid, dim3(kGramWG), 0, s, Vp, stride, Wp, n, b, k,   \
+                     rows_per_wg, partials)
   if (b == 16) {  // whole 16 x 16 MFMA tiles; zero V tiles past k
     const int npg = std::min(kGramPG, (k + 15) / 16);
     if (npg == 1) FE_GRAM(gram16_kernel, 1);
@@ -389,9 +390,18 @@ fe_status gram_t(const void* V, int32_t nblk, int64_t stride, const void* W, int
     else if (npg == 3) FE_GRAM(gram16_kernel, 3);
     else FE_GRAM(gram16_kernel, 4);
   } else if (b % 4 == 0) {  // 16-byte row loads and quad transposes
-    if (b == 4) FE_GRAM(gram_wide_kernel, 1);
-    else if (b == 8) FE_GRAM(gram_wide_kernel, 2);
-    else FE_GRAM(gram_wide_kernel, 4);  // 16 W columns per z-slice
+    // NPG: 16-column V groups per slice, a template parameter so that no MFMA
+    // chain is guarded (groups past k are fed zeros)
+    const int npg = std::min(kGramPG, (k + 15) / 16);
+#define FE_GRAM_W(Q)                                                                          \
+  if (npg == 1) FE_GRAM2(gram_wide_kernel, Q, 1);                                             \
+  else if (npg == 2) FE_GRAM2(gram_wide_kernel, Q, 2);                                        \
+  else if (npg == 3) FE_GRAM2(gram_wide_kernel, Q, 3);                                        \
+  else FE_GRAM2(gram_wide_kernel, Q, 4);
+    if (b == 4) { FE_GRAM_W(1) }
+    else if (b == 8) { FE_GRAM_W(2) }
+    else { FE_GRAM_W(4) }  // 16 W columns per z-slice
+#undef FE_GRAM_W
   } else if (b <= 4) {
     FE_GRAM(gram_kernel, 1);
   } else if (b <= 8) {
@@ -400,6 +410,7 @@ fe_status gram_t(const void* V, int32_t nblk, int64_t stride, const void* W, int
     FE_GRAM(gram_kernel, 4);
   }
 #undef FE_GRAM
+#undef FE_GRAM2
   FE_HIP(hipGetLastError());
   const int len = k * b;
   hipLaunchKernelGGL(reduce_partials, dim3((len + 63) / 64), dim3(1024), 0, s, partials, gx, len,
