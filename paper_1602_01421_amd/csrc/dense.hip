@@ -263,6 +263,133 @@ __global__ __launch_bounds__(kGramWG) void gram_wide_kernel(const T* __restrict_
   }
 }
 
+// CGS2's middle step at b = 4 in one pass over [V W]: W <- W - V C1 and the
+// Gram partials of [V W']^T W' (the layout of gram_wide_kernel<T, 1, NPG>).
+// V has kv columns; W is V's block kv/4, so the lanes whose column group is
+// W's load its old values.  Each lane forms, in FP64, the dot products of its
+// 16 V columns with C1 (staged in LDS, zero past kv); a butterfly over the
+// four lanes holding the row's other column groups completes them.  W' is
+// rounded to T once: that value is stored (by one lane per row) and is what
+// the Gram contracts, both as the last V group and as the W operand.  Rows
+// of a wavefront are its own, so reading W before writing it is safe.
+template <typename T, int NPG>
+__global__ __launch_bounds__(kGramWG) void cgs_mid_kernel(const T* __restrict__ V, int64_t stride,
+                                                          T* __restrict__ W, int64_t n, int32_t kv,
+                                                          const double* __restrict__ C1,
+                                                          int64_t rows_per_wg,
+                                                          double* __restrict__ partials) {
+  using A = typename Acc<T>::type;
+  constexpr int VEC = 16 / sizeof(T) < 4 ? 16 / sizeof(T) : 4;
+  constexpr int B = 4;
+  const int k = kv + B;
+  __shared__ double Cs[16 * NPG * B];  // C1 rows, zero from row kv on
+  for (int i = threadIdx.x; i < 16 * NPG * B; i += kGramWG) Cs[i] = (i / B < kv) ? C1[i] : 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kk = lane >> 4, blk = (lane >> 2) & 3, x = lane & 3;
+  int64_t aoff[NPG];
+  bool aval[NPG], isw[NPG];
+#pragma unroll
+  for (int pg = 0; pg < NPG; ++pg) {
+    const int c0 = pg * 16 + 4 * blk;
+    aval[pg] = c0 < k;
+    isw[pg] = c0 == kv;
+    aoff[pg] = aval[pg] ? (int64_t)(c0 / B) * stride + (c0 % B) : 0;
+  }
+  double acc[NPG];
+#pragma unroll
+  for (int pg = 0; pg < NPG; ++pg) acc[pg] = 0.0;
+  const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r_end = min(n, r_begin + rows_per_wg);
+  for (int64_t r0 = r_begin + wave * kGramRowsPerIter; r0 < r_end;
+       r0 += (kGramWG / 64) * kGramRowsPerIter) {
+    const int64_t row = r0 + 4 * x + kk;  // the row this lane loads
+    const bool rv = row < r_end;
+    const int64_t rb = (rv ? row : r_end - 1) * B;
+    A v[NPG][4], w[4];
+#pragma unroll
+    for (int pg = 0; pg < NPG; ++pg) {
+#pragma unroll
+      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(V + aoff[pg] + rb + c, v[pg] + c);
+      const bool ok = rv && aval[pg];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[pg][c] = ok ? v[pg][c] : (A)0;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(W + rb + c, w + c);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w[c] = rv ? w[c] : (A)0;
+    // V C1 over this lane's columns, then over the row's four lanes
+    double s[B] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int pg = 0; pg < NPG; ++pg)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int col = pg * 16 + 4 * blk + c;
+        const double vv = (col < kv) ? (double)v[pg][c] : 0.0;
+        const double* cr = Cs + col * B;
+#pragma unroll
+        for (int j = 0; j < B; ++j) s[j] = fma(vv, cr[j], s[j]);
+      }
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      s[j] += __shfl_xor(s[j], 4, 64);
+      s[j] += __shfl_xor(s[j], 8, 64);
+    }
+    double d[B];
+    A wr[4];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      d[j] = (double)w[j] - s[j];
+      const T t = to_storage<T, double>(d[j]);
+      if constexpr (sizeof(T) == 2)
+        wr[j] = (A)bf16_to_f32(t);
+      else
+        wr[j] = (A)t;
+      d[j] = (double)wr[j];
+    }
+    if (blk == 0 && rv) {
+#pragma unroll
+      for (int c = 0; c < 4; c += VEC) store_vec<T, VEC, double>(W + rb + c, d + c);
+    }
+    double a[4][NPG], bb[4];
+#pragma unroll
+    for (int pg = 0; pg < NPG; ++pg) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[pg][c] = isw[pg] ? wr[c] : v[pg][c];
+      quad_transpose(v[pg], x);  // v[u] = element (row r0 + 4u + kk, column c0 + x)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u][pg] = (double)v[pg][u];
+    }
+    {
+      A t[4] = {wr[0], wr[1], wr[2], wr[3]};
+      quad_transpose(t, x);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) bb[u] = (double)t[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int pg = 0; pg < NPG; ++pg)
+        acc[pg] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u][pg], bb[u], acc[pg], 0, 0, 0);
+  }
+  __shared__ double red[NPG][64];
+  for (int wv = 0; wv < kGramWG / 64; ++wv) {
+    if (wave == wv) {
+#pragma unroll
+      for (int pg = 0; pg < NPG; ++pg) red[pg][lane] = (wv == 0 ? 0.0 : red[pg][lane]) + acc[pg];
+    }
+    __syncthreads();
+  }
+  double* out = partials + (int64_t)blockIdx.x * k * B;
+  for (int idx = threadIdx.x; idx < NPG * 64; idx += kGramWG) {
+    const int l = idx & 63, pg = idx >> 6;
+    const int i = l >> 4, bl = (l >> 2) & 3, j = l & 3;
+    const int p = pg * 16 + 4 * bl + i;
+    if (p < k) out[(int64_t)p * B + j] = red[pg][l];
+  }
+}
+
 // C[e] = alpha * sum over partial sets x (fixed order: strided lanes, then group order)
 __global__ __launch_bounds__(1024) void reduce_partials(const double* __restrict__ partials,
                                                         int32_t nsets, int32_t len, double alpha,
@@ -945,6 +1072,44 @@ fe_status gram_launch(const void* V, int32_t nblk, int64_t stride, const void* W
     case FE_BF16: return gram_t<bf16_t>(V, nblk, stride, W, n, b, alpha, C, partials, s);
   }
   return fail(FE_EINVAL, "gram: bad dtype");
+}
+
+template <typename T>
+fe_status cgs_mid_t(void* W, int64_t n, const void* V, int32_t nblk_v, int64_t stride,
+                    const double* C1, double* Cout, double* partials, hipStream_t s) {
+  const int32_t kv = nblk_v * 4, k = kv + 4;
+  if (k > 16 * kGramPG) return fail(FE_EUNSUPPORTED, "cgs_mid: %d columns (max %d)", k, 16 * kGramPG);
+  const int gx = gram_sets(n);
+  int64_t rows_per_wg = (n + gx - 1) / gx;
+  rows_per_wg = (rows_per_wg + 15) / 16 * 16;
+  const T* Vp = static_cast<const T*>(V);
+  T* Wp = static_cast<T*>(W);
+  const int npg = (k + 15) / 16;
+#define FE_MID(P)                                                                              \
+  hipLaunchKernelGGL((cgs_mid_kernel<T, P>), dim3(gx), dim3(kGramWG), 0, s, Vp, stride, Wp, n, \
+                     kv, C1, rows_per_wg, partials)
+  if (npg == 1) FE_MID(1);
+  else if (npg == 2) FE_MID(2);
+  else if (npg == 3) FE_MID(3);
+  else FE_MID(4);
+#undef FE_MID
+  FE_HIP(hipGetLastError());
+  const int len = k * 4;
+  hipLaunchKernelGGL(reduce_partials, dim3((len + 63) / 64), dim3(1024), 0, s, partials, gx, len,
+                     1.0, Cout);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+fe_status cgs_mid_launch(void* W, int64_t n, const void* V, int32_t nblk_v, int64_t stride,
+                         const double* C1, double* Cout, double* partials, fe_dtype dt,
+                         hipStream_t s) {
+  switch (dt) {
+    case FE_F64: return cgs_mid_t<double>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
+    case FE_F32: return cgs_mid_t<float>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
+    case FE_BF16: return cgs_mid_t<bf16_t>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
+  }
+  return fail(FE_EINVAL, "cgs_mid: bad dtype");
 }
 
 fe_status update_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk, int64_t stride,

@@ -318,8 +318,18 @@ class Solver {
     double* dC2 = dC + (size_t)(k + b) * b;
     double* flag = rec + (size_t)m * b + (size_t)b * b;
     FE_TRY(gram(nk + 1, W, dC1));
-    FE_TRY(update(W, V, nk, dC1, -1.0, 1.0));
-    FE_TRY(gram(nk + 1, W, dC2));
+    if (b == 4 && k + b <= 64) {
+      // first update and second Gram in one pass over [V W]
+      prof.begin(P_GRAM);
+      FE_TRY(cgs_mid_launch(W, n, V, nk, stride, dC1, dC2, dPart, dt, s));
+      prof.end();
+      ++gram_calls;
+      ++update_calls;
+      bytes[P_GRAM] += (double)n * (nk + 2) * b * es;  // [V W] read, W' written
+    } else {
+      FE_TRY(update(W, V, nk, dC1, -1.0, 1.0));
+      FE_TRY(gram(nk + 1, W, dC2));
+    }
     FE_TRY(update(W, V, nk, dC2, -1.0, 1.0));
     FE_TRY(chol_first_launch(dC1, dC2, k, b, eta, rec, dR1, dM, flag, s));
     FE_TRY(update(W, W, 1, dM, 1.0, 0.0));
