@@ -303,6 +303,7 @@ __global__ __launch_bounds__(kGramWG) void cgs_mid_kernel(const T* __restrict__ 
   const int64_t r_end = min(n, r_begin + rows_per_wg);
   for (int64_t r0 = r_begin + wave * kGramRowsPerIter; r0 < r_end;
        r0 += (kGramWG / 64) * kGramRowsPerIter) {
+    asm volatile("" ::: "memory");  // keep the C1 reads inside the loop (no hoisting)
     const int64_t row = r0 + 4 * x + kk;  // the row this lane loads
     const bool rv = row < r_end;
     const int64_t rb = (rv ? row : r_end - 1) * B;
