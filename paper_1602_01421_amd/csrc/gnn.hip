@@ -163,6 +163,9 @@ __global__ __launch_bounds__(256) void layer_fwd_kernel(const float* __restrict_
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, kg = lane >> 4;
   for (int64_t tile = blockIdx.x; tile * 64 < n; tile += gridDim.x) {
+    // At 64 input features the compiler would hoist every LDS weight read out
+    // of the row-tile loop (100-174 VGPRs); a compiler barrier keeps them inside.
+    if constexpr (DIN > 16) asm volatile("" ::: "memory");
     const int64_t r0 = tile * 64 + wave * 16;
     const int64_t row = r0 + i;
     const int64_t rc = row < n ? row : n - 1;
@@ -229,6 +232,9 @@ __global__ __launch_bounds__(256) void layer_fwd_f32_kernel(const float* __restr
   const int i = lane & 15, kk = lane >> 4;
   const int k0 = KQ * kk;
   for (int64_t tile = blockIdx.x; tile * 64 < n; tile += gridDim.x) {
+    // At 64 input features the compiler would hoist every LDS weight read out
+    // of the row-tile loop (100-174 VGPRs); a compiler barrier keeps them inside.
+    if constexpr (DIN > 16) asm volatile("" ::: "memory");
     const int64_t r0 = tile * 64 + wave * 16;
     const int64_t row = r0 + i;
     const int64_t rc = row < n ? row : n - 1;
@@ -291,6 +297,9 @@ __global__ __launch_bounds__(256) void layer_bwd_kernel(const float* __restrict_
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, kk = lane >> 4;
   for (int64_t tile = blockIdx.x; tile * 64 < n; tile += gridDim.x) {
+    // At 64 input features the compiler would hoist every LDS weight read out
+    // of the row-tile loop (100-174 VGPRs); a compiler barrier keeps them inside.
+    if constexpr (DIN > 16) asm volatile("" ::: "memory");
     const int64_t r0 = tile * 64 + wave * 16;
     const int64_t row = r0 + i;
     const int64_t rc = row < n ? row : n - 1;
