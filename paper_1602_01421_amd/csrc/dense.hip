@@ -1079,7 +1079,7 @@ template <typename T>
 fe_status cgs_mid_t(void* W, int64_t n, const void* V, int32_t nblk_v, int64_t stride,
                     const double* C1, double* Cout, double* partials, hipStream_t s) {
   const int32_t kv = nblk_v * 4, k = kv + 4;
-  if (k > 16 * kGramPG) return fail(FE_EUNSUPPORTED, "cgs_mid: %d columns (max %d)", k, 16 * kGramPG);
+  if (k > 128) return fail(FE_EUNSUPPORTED, "cgs_mid: %d columns (max 128)", k);
   const int gx = gram_sets(n);
   int64_t rows_per_wg = (n + gx - 1) / gx;
   rows_per_wg = (rows_per_wg + 15) / 16 * 16;
@@ -1089,10 +1089,16 @@ fe_status cgs_mid_t(void* W, int64_t n, const void* V, int32_t nblk_v, int64_t s
 #define FE_MID(P)                                                                              \
   hipLaunchKernelGGL((cgs_mid_kernel<T, P>), dim3(gx), dim3(kGramWG), 0, s, Vp, stride, Wp, n, \
                      kv, C1, rows_per_wg, partials)
-  if (npg == 1) FE_MID(1);
-  else if (npg == 2) FE_MID(2);
-  else if (npg == 3) FE_MID(3);
-  else FE_MID(4);
+  switch (npg) {
+    case 1: FE_MID(1); break;
+    case 2: FE_MID(2); break;
+    case 3: FE_MID(3); break;
+    case 4: FE_MID(4); break;
+    case 5: FE_MID(5); break;
+    case 6: FE_MID(6); break;
+    case 7: FE_MID(7); break;
+    default: FE_MID(8); break;
+  }
 #undef FE_MID
   FE_HIP(hipGetLastError());
   const int len = k * 4;

@@ -98,7 +98,7 @@ fe_status update_gram_launch(void* W, int64_t n, int32_t b, const void* V, int32
                              fe_dtype dt, hipStream_t s);
 // CGS2's middle step at b = 4 (solver-internal): W <- W - V[:, :4 nblk_v] C1,
 // then Cout ((4 nblk_v + 4) x 4) = [V W']^T W' with the rounded W'; W is V's
-// block nblk_v.  FE_EUNSUPPORTED beyond 64 columns.  partials as for gram_launch.
+// block nblk_v.  FE_EUNSUPPORTED beyond 128 columns.  partials as for gram_launch.
 fe_status cgs_mid_launch(void* W, int64_t n, const void* V, int32_t nblk_v, int64_t blk_stride,
                          const double* C1, double* Cout, double* partials, fe_dtype dt,
                          hipStream_t s);

@@ -251,10 +251,11 @@ def test_start_block_with_nan_and_repeated_columns(fe):
     assert np.allclose(r.evals, ref.evals, rtol=1e-10)
 
 
-@pytest.mark.parametrize("nev,b,m", [(4, 1, 24), (6, 2, 32), (8, 16, 64)])
+@pytest.mark.parametrize("nev,b,m", [(4, 1, 24), (6, 2, 32), (8, 16, 64), (8, 4, 112)])
 def test_block_widths_fp64_match_oracle(fe, nev, b, m):
-    """Block widths 1, 2 (element-load Gram) and 16 (widest factor kernels):
-    FP64 storage, same start block as the oracle: same products, eigenvalues
+    """Block widths 1, 2 (element-load Gram), 16 (widest factor kernels) and
+    4 with m 112 (the fused CGS2 middle step up to 116 columns): FP64
+    storage, same start block as the oracle: same products, eigenvalues
     within 1e-10."""
     g = S.chung_lu_edges(30000, alpha=2.2, mean_deg=12, seed=17)
     A, rp, ci = setup(fe, g)
