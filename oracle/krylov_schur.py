@@ -29,6 +29,20 @@ Restart: keep p = m - b*max(1, floor((m - nev)/(2b))) Ritz vectors (reading):
   V <- V Y[:, :p], T <- diag(theta_1..p), B <- B Y[:, :p], k = p.
 Final check: X = V Y[:, :nev], explicit residual
   ||A x_i - theta_i x_i|| / (max(eps^(2/3), |theta_i|) ||x_i||).
+
+Block QR thresholds (reading; the paper does not describe breakdown):
+  eta (refill): column j of the new block is dependent when its norm after
+  projection against V and the earlier accepted columns is <= eta times its
+  norm before projection, or is not finite.  A refill discards that residual
+  part, so A V = V T + Q B then holds only up to eta ||A q_j|| <= eta ||A||
+  per refilled column, an error the estimates rho do not see (the explicit
+  residuals of the final check do).  eta = 1e-10 keeps it far below every
+  tolerance used; exact breakdowns (invariant subspaces of closed-form
+  graphs) give ratios near the unit roundoff.
+  eta_chol (factorisation): Cholesky QR twice is stable only while the
+  block's condition number stays well below u^(-1/2) (Yamamoto, Nakatsukasa,
+  Yanagisawa and Fukaya, 2015); when some column-wise ratio is below
+  eta_chol = 1e-6 the column-wise Gram-Schmidt factors are kept instead.
 """
 from __future__ import annotations
 
@@ -83,13 +97,16 @@ def _columnwise(W: np.ndarray, nb: np.ndarray, eta: float):
     """Column-wise CGS2 of W in column order (W already projected against V).
 
     Column j is dependent when its norm after projection against the earlier
-    accepted columns is <= eta * nb[j] (nb = norm before any projection).
-    Returns Q (dependent columns zero), R (dependent rows zero), accepted, dependent.
+    accepted columns is not above eta * nb[j] (nb = norm before any
+    projection), which includes a non-finite column.
+    Returns Q (dependent columns zero), R (dependent rows zero), accepted,
+    dependent, and the ratio norm-after / norm-before of every column.
     """
     n, b = W.shape
     Q = np.zeros_like(W)
     R = np.zeros((b, b))
     acc, dep = [], []
+    ratio = np.zeros(b)
     for j in range(b):
         w = W[:, j].copy()
         if acc:
@@ -100,27 +117,32 @@ def _columnwise(W: np.ndarray, nb: np.ndarray, eta: float):
             w -= Qa @ c2
             R[acc, j] = c1 + c2
         nw = np.sqrt(w @ w)
-        if nw <= eta * nb[j] or nw == 0.0:
+        ratio[j] = nw / nb[j] if nb[j] > 0 else 0.0
+        if not (nw > eta * nb[j]) or nw == 0.0:
             dep.append(j)
         else:
             Q[:, j] = w / nw
             R[j, j] = nw
             acc.append(j)
-    return Q, R, acc, dep
+    return Q, R, acc, dep, ratio
 
 
-def _block_qr(Vk: np.ndarray, W: np.ndarray, nb: np.ndarray, eta: float, seed: int, step: int):
+def _block_qr(Vk: np.ndarray, W: np.ndarray, nb: np.ndarray, eta: float, seed: int, step: int,
+              eta_chol: float = 1e-6):
     """Orthonormalise W (already projected against Vk).  Returns Q, R, refill count.
 
     Dependence is decided column by column (reading).  With no dependent
-    column the factorisation is CholQR2: R1 = chol(W^T W), W <- W R1^-1,
-    R2 = chol(W^T W), Q = W R2^-1, R = R2 R1.  Otherwise the column-wise
-    result is kept; each dependent column has R[j, :] = 0 and is replaced, after
-    all independent columns are fixed and in column order, by a random vector
-    orthogonalised (twice) against Vk and every column defined so far.
+    column and every column-wise ratio >= eta_chol the factorisation is
+    CholQR2: R1 = chol(W^T W), W <- W R1^-1, R2 = chol(W^T W), Q = W R2^-1,
+    R = R2 R1.  Otherwise the column-wise result is kept; each dependent
+    column has R[j, :] = 0 and is replaced, after all independent columns are
+    fixed and in column order, by a random vector orthogonalised (twice)
+    against Vk and every column defined so far.
     """
     n, b = W.shape
-    Qc, Rc, acc, dep = _columnwise(W, nb, eta)
+    Qc, Rc, acc, dep, ratio = _columnwise(W, nb, eta)
+    if not dep and ratio.min() < eta_chol:
+        return Qc, Rc, 0
     if not dep:
         try:
             R1 = _chol_upper(W.T @ W)
@@ -148,7 +170,8 @@ def _ritz_order(theta: np.ndarray) -> np.ndarray:
 
 
 def krylov_schur(spmm, n: int, nev: int, b: int, m: int, tol: float, X0: np.ndarray,
-                 max_restarts: int = 500, seed: int = 0, eta: float = 1e-6) -> KSResult:
+                 max_restarts: int = 500, seed: int = 0, eta: float = 1e-10,
+                 eta_chol: float = 1e-6) -> KSResult:
     """spmm(X) must return A @ X for an (n, cols) float64 array."""
     if m % b or nev > m - b or nev < 1 or tol <= 0 or m + b > n:
         raise ValueError("need m % b == 0, 1 <= nev <= m - b, tol > 0, m + b <= n")
@@ -157,7 +180,7 @@ def krylov_schur(spmm, n: int, nev: int, b: int, m: int, tol: float, X0: np.ndar
     Bk = np.zeros((b, m))
     X0 = np.array(X0, dtype=np.float64, copy=True)
     Q, _, refills = _block_qr(np.zeros((n, 0)), X0, np.sqrt(np.sum(X0 * X0, axis=0)), eta,
-                              seed, 0)
+                              seed, 0, eta_chol)
     k = 0
     step = 0
     spmm_calls = 0
@@ -173,7 +196,7 @@ def krylov_schur(spmm, n: int, nev: int, b: int, m: int, tol: float, X0: np.ndar
             Vk = V[:, :k]
             nb = np.sqrt(np.sum(W * W, axis=0))
             C = _cgs2(Vk, W)
-            Q, R, nref = _block_qr(Vk, W, nb, eta, seed, step)
+            Q, R, nref = _block_qr(Vk, W, nb, eta, seed, step, eta_chol)
             refills += nref
             T[:k, k - b:k] = C
             T[k - b:k, :k] = C.T

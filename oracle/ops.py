@@ -49,14 +49,22 @@ def col_norms(X: np.ndarray) -> np.ndarray:
 
 
 def round_bf16(x: np.ndarray) -> np.ndarray:
-    """Round to bfloat16 (round to nearest, ties to even, on the FP32 bit
-    pattern: add 0x7FFF plus the lowest kept bit, clear the low 16 bits).
-    Exact for inputs that are exactly representable in FP32."""
-    f = np.asarray(x, dtype=np.float32)
-    u = f.view(np.uint32).astype(np.uint64)
-    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
-    out = u.astype(np.uint32).view(np.float32).astype(np.float64)
-    return np.where(np.isfinite(f), out, f.astype(np.float64))
+    """Round to bfloat16: the nearest number with 8 significant bits in FP32's
+    exponent range (normal exponents -126..127, subnormal spacing 2^-133),
+    ties to the even last bit, one rounding from the input's exact value;
+    results past the largest finite value become infinite.  Zeros keep their
+    sign; NaN and infinities pass through.  Returns float64."""
+    x = np.asarray(x, dtype=np.float64)
+    out = x.copy()
+    fin = np.isfinite(x) & (x != 0.0)
+    ax = np.abs(x[fin])
+    _, E = np.frexp(ax)                      # ax = f * 2^E, f in [0.5, 1)
+    e = np.maximum(E - 1, -126)              # exponent of the leading bit, clamped
+    q = np.ldexp(ax, 7 - e)                  # exact: ax in units of the last kept bit
+    y = np.ldexp(np.rint(q), e - 7)          # rint rounds half to even
+    y[y >= 2.0 ** 128] = np.inf
+    out[fin] = np.copysign(y, x[fin])
+    return out
 
 
 def spmm_rows_from_edges(n: int, src: np.ndarray, dst: np.ndarray, X: np.ndarray,

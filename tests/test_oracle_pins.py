@@ -301,10 +301,10 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
     elif mutation == "transpose":  # Cholesky factor used untransposed
         monkeypatch.setattr(K, "_chol_upper", lambda G: np.linalg.cholesky(G))
     elif mutation == "bad_refill":  # refill without orthogonalising
-        def refill_not_orthogonal(Vk, W, nb, eta, seed, step):
-            Q, R, acc, dep = K._columnwise(W, nb, eta)
+        def refill_not_orthogonal(Vk, W, nb, eta, seed, step, eta_chol=1e-6):
+            Q, R, acc, dep, _ = K._columnwise(W, nb, eta)
             if not dep:
-                return K._block_qr.__wrapped__(Vk, W, nb, eta, seed, step)
+                return K._block_qr.__wrapped__(Vk, W, nb, eta, seed, step, eta_chol)
             for j in dep:
                 Q[:, j] = 1.0 / np.sqrt(W.shape[0])
             return Q, R, len(dep)
