@@ -172,7 +172,12 @@ typedef struct {
   const void *start;     /* device n x block start block in dt, original vertex
                             order; NULL = N(0,1) drawn from `seed` */
   void *hip_stream;      /* stream for all work (NULL = null stream) */
-  double eta;            /* dependence threshold; 0 -> 1e-6 (F64), 1e-5 (F32), 3e-2 (BF16) */
+  double eta;            /* refill threshold: a new column whose norm after projection
+                            (against the basis and the block's earlier kept columns,
+                            column by column) is <= eta x its norm before is refilled;
+                            0 -> 1e-10 (F64), 1e-5 (F32), 3e-2 (BF16).  Blocks with a
+                            column ratio below max(eta, 1e-6) are factored column by
+                            column instead of by Cholesky QR twice. */
   int32_t profile;       /* 1 = time each kernel class with HIP events */
   int32_t verbose;       /* 1 = print one line per restart to stderr */
   int32_t mixed;         /* 1 = mixed-precision storage: the subspace starts in BF16;

@@ -20,11 +20,11 @@
 //
 // Readings where the paper is silent: dependence threshold eta (a column is
 // dependent when its norm after projection against V and the earlier
-// accepted columns is <= eta times its norm before projection; the test is
-// taken on the Gram matrix, whose cancellation resolves ratios down to about
-// sqrt(FP64 unit roundoff) = 1.5e-8, so eta >= 1e-6); dependent
-// columns are refilled with Philox uniform [-1, 1) draws orthogonalised
-// against everything accepted; kept Ritz vectors p = m - b*max(1,
+// accepted columns is <= eta times its norm before projection; 1e-10 for
+// FP64 storage, decided with directly computed norms), and a Cholesky QR
+// guard eta_chol = 1e-6 below which the column-wise factors replace Cholesky
+// QR twice (see set_eta); dependent columns are refilled with Philox uniform
+// [-1, 1) draws orthogonalised against everything accepted; kept Ritz vectors p = m - b*max(1,
 // floor((m-nev)/(2b))); convergence rho_i <= tol * max(eps^(2/3), |theta_i|)
 // with eps the FP64 unit roundoff (ARPACK's convention).
 #include <algorithm>
@@ -141,7 +141,7 @@ class Solver {
  public:
   const Csr& A;
   int nev, b, m;
-  double tol, eta;
+  double tol, eta, eta_chol;
   fe_ks_opts o;
   hipStream_t s;
   fe_dtype dt, dt_final;
@@ -183,7 +183,17 @@ class Solver {
     prof.s = s;
   }
 
-  void set_eta() { eta = o.eta > 0 ? o.eta : (dt == FE_F64 ? 1e-6 : dt == FE_F32 ? 1e-5 : 3e-2); }
+  // eta: refill threshold on the column-wise ratio (reading: 1e-10 for FP64
+  // storage, 1e-5 FP32, 3e-2 BF16, near each storage's rounding level);
+  // eta_chol: below this ratio Cholesky QR twice is not trusted (its first
+  // pass loses orthogonality like u kappa^2), and the device path hands the
+  // step to the column-wise path.  The device screen reads the ratio from a
+  // Schur complement of the Gram matrix, which resolves it down to about
+  // sqrt(u) = 1.5e-8, so eta_chol >= 1e-6.
+  void set_eta() {
+    eta = o.eta > 0 ? o.eta : (dt == FE_F64 ? 1e-10 : dt == FE_F32 ? 1e-5 : 3e-2);
+    eta_chol = std::max(eta, 1e-6);
+  }
 
   void* blk(int j) { return V + (size_t)j * stride * es; }
 
@@ -331,7 +341,7 @@ class Solver {
       FE_TRY(gram(nk + 1, W, dC2));
     }
     FE_TRY(update(W, V, nk, dC2, -1.0, 1.0));
-    FE_TRY(chol_first_launch(dC1, dC2, k, b, eta, rec, dR1, dM, flag, s));
+    FE_TRY(chol_first_launch(dC1, dC2, k, b, eta_chol, rec, dR1, dM, flag, s));
     FE_TRY(update(W, W, 1, dM, 1.0, 0.0));
     prof.begin(P_GRAM);
     FE_TRY(gram_launch(W, 1, stride, W, n, b, dt, 1.0, dC, dPart, s));
@@ -356,15 +366,102 @@ class Solver {
     t_host += secs(th, clk::now());
   }
 
+  // W <- W * M with M the identity except the entries set by the caller
+  // (hM is reset to the identity by reset_M).
+  void reset_M() {
+    std::fill(hM, hM + b * b, 0.0);
+    for (int i = 0; i < b; ++i) hM[i * b + i] = 1.0;
+  }
+
+  // Column j of block wb against the accepted (orthonormal) columns `acc`,
+  // twice (classical Gram-Schmidt twice); the coefficients are added to
+  // R[acc, j].  Returns the norm of the projected column, taken directly
+  // from the block's own Gram matrix (no cancellation against earlier norms).
+  fe_status project_column(int wb, int j, const std::vector<int>& acc, std::vector<double>& R,
+                           double* norm) {
+    void* W = blk(wb);
+    for (int pass = 0; pass < 2 && !acc.empty(); ++pass) {
+      FE_TRY(self_gram(wb));
+      reset_M();
+      for (int i : acc) {
+        const double c = hG[i * b + j];
+        hM[i * b + j] = -c;
+        R[(size_t)i * b + j] += c;
+      }
+      FE_TRY(right_mult(W));
+    }
+    FE_TRY(self_gram(wb));
+    *norm = std::sqrt(std::max(0.0, hG[j * b + j]));
+    return FE_OK;
+  }
+
+  fe_status scale_column(int wb, int j, double f) {
+    reset_M();
+    hM[j * b + j] = f;
+    return right_mult(blk(wb));
+  }
+
+  // Cholesky QR twice of block wb in place: R (b x b) with W_in = Q R.
+  // Returns false (W untouched) when a factorisation fails.
+  fe_status cholqr2(int wb, std::vector<double>& R, bool* ok) {
+    std::vector<double> Rt((size_t)b * b, 0.0), Racc((size_t)b * b, 0.0), Ri((size_t)b * b);
+    for (int i = 0; i < b; ++i) Racc[i * b + i] = 1.0;
+    *ok = false;
+    for (int pass = 0; pass < 2; ++pass) {
+      FE_TRY(self_gram(wb));
+      std::fill(Rt.begin(), Rt.end(), 0.0);
+      for (int j = 0; j < b; ++j) {
+        double d = hG[j * b + j];
+        for (int i = 0; i < j; ++i) d -= Rt[i * b + j] * Rt[i * b + j];
+        if (!(d > 0.0)) {
+          if (pass == 1) return fail(FE_EBREAKDOWN, "fe_krylov_schur: block QR lost rank (step %d)", step);
+          return FE_OK;
+        }
+        Rt[j * b + j] = std::sqrt(d);
+        for (int l = j + 1; l < b; ++l) {
+          double g = hG[j * b + l];
+          for (int i = 0; i < j; ++i) g -= Rt[i * b + j] * Rt[i * b + l];
+          Rt[j * b + l] = g / Rt[j * b + j];
+        }
+      }
+      inv_upper(b, Rt.data(), b, Ri.data(), b);
+      std::copy(Ri.begin(), Ri.end(), hM);
+      FE_TRY(right_mult(blk(wb)));
+      std::vector<double> tmp((size_t)b * b, 0.0);  // Racc <- Rt Racc
+      for (int i = 0; i < b; ++i)
+        for (int j = 0; j < b; ++j) {
+          double sum = 0.0;
+          for (int t = 0; t < b; ++t) sum += Rt[i * b + t] * Racc[t * b + j];
+          tmp[i * b + j] = sum;
+        }
+      Racc.swap(tmp);
+    }
+    R = Racc;
+    *ok = true;
+    return FE_OK;
+  }
+
   // Orthogonalise W (block wb) against V[:, :k] (blocks 0..k/b-1, k = wb*b) and
   // orthonormalise it.  Out: C (k x b) and R (b x b) with W_in = V C + Q R.
+  // The careful path, taken for the start block and for every step the
+  // device-side factors flagged: CGS2 against V, then column-wise CGS2 inside
+  // the block in column order with each column's norm read directly from the
+  // block's Gram matrix, so that the dependence ratio (norm after projection
+  // over norm before) is resolved down to the storage's rounding, not to the
+  // square root of it as a Schur complement of the Gram matrix would be.
+  // Column j is dependent when that ratio is not above eta (or the column is
+  // not finite): its row of R is zero and it is refilled with Philox draws
+  // orthogonalised against V and every column kept so far.  With no
+  // dependent column and every ratio at least eta_chol the block is
+  // refactored by Cholesky QR twice (the device path's factorisation);
+  // otherwise the column-wise factors stand.
   fe_status orth_block(int wb, std::vector<double>& C, std::vector<double>& R) {
     const int nk = wb;  // basis blocks
     const int k = nk * b;
     void* W = blk(wb);
     double* dC1 = dC;
     double* dC2 = dC + (size_t)(k + b) * b;
-    // pass 1: [V W]^T W
+    // CGS2 against V: pass 1 gives [V W]^T W (W's own norms in its last rows)
     FE_TRY(gram(nk + 1, W, dC1));
     FE_HIP(hipMemcpyAsync(hC1, dC1, sizeof(double) * (k + b) * b, hipMemcpyDeviceToHost, s));
     if (nk > 0) {
@@ -374,128 +471,79 @@ class Solver {
       FE_TRY(update(W, V, nk, dC2, -1.0, 1.0));
     }
     FE_TRY(sync());
-    auto th = clk::now();
-    std::vector<double> nb(b), G((size_t)b * b);
+    std::vector<double> nb(b);
     for (int j = 0; j < b; ++j) nb[j] = std::sqrt(std::max(0.0, hC1[(size_t)(k + j) * b + j]));
     C.assign((size_t)k * b, 0.0);
-    if (nk > 0) {
-      for (int i = 0; i < k * b; ++i) C[i] = hC1[i] + hC2[i];
-      // G = W2^T W2 = W1^T W1 - C2^T C2 (V orthonormal)
-      for (int i = 0; i < b; ++i)
-        for (int j = 0; j < b; ++j) {
-          double g = hC2[(size_t)(k + i) * b + j];
-          for (int t = 0; t < k; ++t) g -= hC2[(size_t)t * b + i] * hC2[(size_t)t * b + j];
-          G[i * b + j] = g;
-        }
-    } else {
-      for (int i = 0; i < b * b; ++i) G[i] = hC1[i];
-    }
-    // rank-revealing Cholesky in column order
-    std::vector<double> R1((size_t)b * b, 0.0);
+    for (int i = 0; i < k * b; ++i) C[i] = hC1[i] + (nk > 0 ? hC2[i] : 0.0);
+    // A non-finite column (a caller's start block) is dependent outright and
+    // is overwritten by its refill draws at once: the right multiplications
+    // below combine all columns, and NaN x 0 would spread it.
+    uint32_t bad_mask = 0;
+    for (int j = 0; j < b; ++j)
+      if (!std::isfinite(hC1[(size_t)(k + j) * b + j])) bad_mask |= 1u << j;
+    const int32_t* perm = A.relabeled ? A.d_perm : nullptr;
+    if (bad_mask)
+      FE_TRY(random_fill(W, n, b, bad_mask, 1, o.seed, (uint32_t)step, perm, dt, s));
+    // column-wise CGS2 in column order
+    R.assign((size_t)b * b, 0.0);
     std::vector<int> acc, dep;
+    double min_ratio = 1.0;
     for (int j = 0; j < b; ++j) {
-      double d = G[j * b + j];
-      for (int i : acc) d -= R1[i * b + j] * R1[i * b + j];
-      const double thr = eta * nb[j];
-      if (!(d > thr * thr) || !(d > 0.0)) {
+      if (bad_mask & (1u << j)) {
         dep.push_back(j);
         continue;
       }
-      const double rjj = std::sqrt(d);
-      R1[j * b + j] = rjj;
-      for (int l = j + 1; l < b; ++l) {
-        double g = G[j * b + l];
-        for (int i : acc) g -= R1[i * b + j] * R1[i * b + l];
-        R1[j * b + l] = g / rjj;
+      double nw = 0.0;
+      FE_TRY(project_column(wb, j, acc, R, &nw));
+      min_ratio = std::min(min_ratio, nb[j] > 0.0 ? nw / nb[j] : 0.0);
+      if (!(nw > eta * nb[j]) || !(nw > 0.0)) {
+        dep.push_back(j);
+        continue;
       }
+      FE_TRY(scale_column(wb, j, 1.0 / nw));
+      R[(size_t)j * b + j] = nw;
       acc.push_back(j);
     }
-    const int na = (int)acc.size();
-    // M = R1[acc,acc]^-1 scattered into acc positions (dependent columns -> 0)
-    {
-      std::vector<double> Ra((size_t)na * na), Rai((size_t)na * na);
-      for (int s1 = 0; s1 < na; ++s1)
-        for (int s2 = 0; s2 < na; ++s2) Ra[s1 * na + s2] = R1[acc[s1] * b + acc[s2]];
-      inv_upper(na, Ra.data(), na, Rai.data(), na);
-      std::fill(hM, hM + b * b, 0.0);
-      for (int s1 = 0; s1 < na; ++s1)
-        for (int s2 = 0; s2 < na; ++s2) hM[acc[s1] * b + acc[s2]] = Rai[s1 * na + s2];
-    }
-    t_host += secs(th, clk::now());
-    if (!dep.empty()) {
-      // A dependent column may hold non-finite values (a caller's start block):
-      // overwrite it before the right multiplication, whose zero rows for it
-      // would still carry NaN through (NaN x 0).  The draws are counter-based,
-      // so the refill below writes the same values; for finite inputs the
-      // zero rows contribute exact zeros and nothing changes.
-      uint32_t mask = 0;
-      for (int j : dep) mask |= 1u << j;
-      FE_TRY(random_fill(W, n, b, mask, 1, o.seed, (uint32_t)step, A.relabeled ? A.d_perm : nullptr,
-                         dt, s));
-    }
-    FE_TRY(right_mult(W));
-    // Racc (na x na): accumulated second-stage factor of the accepted columns
-    std::vector<double> Racc((size_t)na * na, 0.0);
-    for (int i = 0; i < na; ++i) Racc[i * na + i] = 1.0;
-    std::vector<int> ord = acc;
-    if (!dep.empty()) {
-      uint32_t mask = 0;
-      for (int j : dep) mask |= 1u << j;
-      FE_TRY(random_fill(W, n, b, mask, 1, o.seed, (uint32_t)step, A.relabeled ? A.d_perm : nullptr,
-                         dt, s));
-      if (nk > 0) {  // project the refills (and, harmlessly, the rest) against V, twice
-        for (int pass = 0; pass < 2; ++pass) {
-          FE_TRY(gram(nk + 1, W, dC2));
-          FE_TRY(update(W, V, nk, dC2, -1.0, 1.0));
+    if (dep.empty()) {
+      if (min_ratio >= eta_chol) {
+        // well conditioned: Cholesky QR twice of the projected block, rebuilt
+        // as Q R from the column-wise factors
+        std::copy(R.begin(), R.end(), hM);
+        FE_TRY(right_mult(W));
+        std::vector<double> Rq;
+        bool ok = false;
+        FE_TRY(cholqr2(wb, Rq, &ok));
+        if (ok) {
+          R = Rq;
+        } else {  // back to the column-wise factors: W <- W R^-1
+          std::vector<double> Ri((size_t)b * b);
+          inv_upper(b, R.data(), b, Ri.data(), b);
+          std::copy(Ri.begin(), Ri.end(), hM);
+          FE_TRY(right_mult(W));
         }
       }
-      refills += (int)dep.size();
-      for (int j : dep) ord.push_back(j);
+      return FE_OK;
     }
-    // Cholesky QR passes in the order `ord` (accepted first): two passes, or
-    // three when refills were added (the refills start far from orthogonal)
-    const int passes = dep.empty() ? 1 : 2;
-    for (int pass = 0; pass < passes; ++pass) {
-      FE_TRY(self_gram(wb));
-      auto th2 = clk::now();
-      std::vector<double> Gp((size_t)b * b), Rp((size_t)b * b, 0.0), Rpi((size_t)b * b);
-      for (int s1 = 0; s1 < b; ++s1)
-        for (int s2 = 0; s2 < b; ++s2) Gp[s1 * b + s2] = hG[ord[s1] * b + ord[s2]];
-      for (int j = 0; j < b; ++j) {
-        double d = Gp[j * b + j];
-        for (int i = 0; i < j; ++i) d -= Rp[i * b + j] * Rp[i * b + j];
-        if (!(d > 0.0))
-          return fail(FE_EBREAKDOWN, "fe_krylov_schur: block QR lost rank (step %d)", step);
-        Rp[j * b + j] = std::sqrt(d);
-        for (int l = j + 1; l < b; ++l) {
-          double g = Gp[j * b + l];
-          for (int i = 0; i < j; ++i) g -= Rp[i * b + j] * Rp[i * b + l];
-          Rp[j * b + l] = g / Rp[j * b + j];
-        }
+    // refills, in column order, against V (twice) and the kept columns (twice)
+    uint32_t mask = 0;
+    for (int j : dep) mask |= 1u << j;
+    FE_TRY(random_fill(W, n, b, mask, 1, o.seed, (uint32_t)step, perm, dt, s));
+    if (nk > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        FE_TRY(gram(nk + 1, W, dC2));
+        FE_TRY(update(W, V, nk, dC2, -1.0, 1.0));
       }
-      inv_upper(b, Rp.data(), b, Rpi.data(), b);
-      for (int s1 = 0; s1 < b; ++s1)
-        for (int s2 = 0; s2 < b; ++s2) hM[ord[s1] * b + ord[s2]] = Rpi[s1 * b + s2];
-      // Racc <- Rp[:na,:na] * Racc
-      std::vector<double> tmp((size_t)na * na, 0.0);
-      for (int i = 0; i < na; ++i)
-        for (int j = 0; j < na; ++j) {
-          double sum = 0.0;
-          for (int t = 0; t < na; ++t) sum += Rp[i * b + t] * Racc[t * na + j];
-          tmp[i * na + j] = sum;
-        }
-      Racc.swap(tmp);
-      t_host += secs(th2, clk::now());
-      FE_TRY(right_mult(W));
     }
-    // R[acc[i], :] = sum_t Racc[i][t] R1[acc[t], :], dependent rows 0
-    R.assign((size_t)b * b, 0.0);
-    for (int i = 0; i < na; ++i)
-      for (int j = 0; j < b; ++j) {
-        double sum = 0.0;
-        for (int t = 0; t < na; ++t) sum += Racc[i * na + t] * R1[acc[t] * b + j];
-        R[acc[i] * b + j] = sum;
-      }
+    for (int j : dep) {
+      std::vector<double> Rdrop((size_t)b * b, 0.0);  // a refill's coefficients are not kept
+      double nw = 0.0;
+      FE_TRY(project_column(wb, j, acc, Rdrop, &nw));
+      if (!(nw > 0.0) || !std::isfinite(nw))
+        return fail(FE_EBREAKDOWN, "fe_krylov_schur: refill of column %d is dependent (step %d)", j, step);
+      FE_TRY(scale_column(wb, j, 1.0 / nw));
+      acc.push_back(j);
+    }
+    refills += (int)dep.size();
     return FE_OK;
   }
 
