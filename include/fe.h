@@ -134,6 +134,23 @@ fe_status fe_gram(const void *V, int32_t nblk, int64_t blk_stride, const void *W
                   int32_t b, fe_dtype dt, double alpha, double *C, void *hip_stream);
 
 /*
+ * fe_gram without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid it).  Same arguments, result and errors as fe_gram, and the same
+ * kernels, so the result is bitwise fe_gram's.  The row-interval partial
+ * sums go to a static device array of 2^20 doubles (8 MiB) that each GPU the
+ * library runs on holds until the process ends, instead of a per-call
+ * buffer.  The partials take min(512, ceil(n/128)) * k * b doubles, so any n
+ * works for k * b <= 2048; larger requests return FE_EUNSUPPORTED before
+ * anything is launched.  Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (other streams, other host threads)
+ * race and must be serialised by the caller.
+ */
+fe_status fe_gram_noalloc(const void *V, int32_t nblk, int64_t blk_stride, const void *W,
+                          int64_t n, int32_t b, fe_dtype dt, double alpha, double *C,
+                          void *hip_stream);
+
+/*
  * W = beta * W + alpha * V C  (MvTimesMatAddMv).  W: device n x b; V: nblk
  * blocks as in fe_gram; C: device FP64 k x b row-major.  FP64 arithmetic,
  * rounded to dt.  Every output row depends only on the same row of V and W

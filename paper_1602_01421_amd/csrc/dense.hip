@@ -1053,6 +1053,10 @@ size_t gram_partials_doubles(int64_t n, int32_t k, int32_t b) {
   return (size_t)std::max(gram_sets(n), ug_sets(n)) * (size_t)k * (size_t)b;
 }
 
+size_t gram_sets_partials_doubles(int64_t n, int32_t k, int32_t b) {
+  return (size_t)gram_sets(n) * (size_t)k * (size_t)b;
+}
+
 fe_status update_gram_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk,
                              int64_t stride, const double* C, double* Cout, double* partials,
                              fe_dtype dt, hipStream_t s) {

@@ -77,8 +77,10 @@ fe_status spmm_launch(const Csr& A, const void* X, void* Y, int32_t b, fe_dtype 
                       hipStream_t s);
 
 // ------------------------------------------------------------- dense side
-// partial buffer size (doubles) needed by gram_launch for (n, k, b)
+// partial buffer size (doubles) needed by gram_launch, update_gram_launch and
+// cgs_mid_launch for (n, k, b); gram_sets_partials_doubles: gram_launch alone
 size_t gram_partials_doubles(int64_t n, int32_t k, int32_t b);
+size_t gram_sets_partials_doubles(int64_t n, int32_t k, int32_t b);
 fe_status gram_launch(const void* V, int32_t nblk, int64_t blk_stride, const void* W, int64_t n,
                       int32_t b, fe_dtype dt, double alpha, double* C, double* partials,
                       hipStream_t s);

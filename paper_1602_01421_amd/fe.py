@@ -22,7 +22,7 @@ FE_SYMMETRIZE, FE_DEDUPE, FE_DROP_SELF, FE_RELABEL_BY_DEGREE = 0x1, 0x2, 0x4, 0x
 FE_GRAPH_DEFAULT = FE_SYMMETRIZE | FE_DEDUPE | FE_DROP_SELF
 
 EXPORTED = ("fe_last_error", "fe_version", "fe_csr_build", "fe_csr_from_csr", "fe_csr_info",
-            "fe_csr_perm", "fe_csr_export", "fe_csr_free", "fe_spmm", "fe_gram",
+            "fe_csr_perm", "fe_csr_export", "fe_csr_free", "fe_spmm", "fe_gram", "fe_gram_noalloc",
             "fe_block_update", "fe_block_update_gram", "fe_krylov_schur", "fe_dense_symeig", "fe_gnn_param_count",
             "fe_gnn_create", "fe_gnn_free", "fe_gnn_get_params", "fe_gnn_set_params",
             "fe_gnn_forward", "fe_gnn_backward", "fe_gnn_adam")
@@ -82,6 +82,7 @@ def lib():
             "fe_csr_export": [P, P, P],
             "fe_spmm": [P, P, P, i32, i32, P],
             "fe_gram": [P, i32, i64, P, i64, i32, i32, f64, P, P],
+            "fe_gram_noalloc": [P, i32, i64, P, i64, i32, i32, f64, P, P],
             "fe_block_update": [P, i64, i32, P, i32, i64, P, f64, f64, i32, P],
             "fe_block_update_gram": [P, i64, i32, P, i32, i64, P, P, i32, P],
             "fe_krylov_schur": [P, i32, i32, i32, f64, ctypes.POINTER(KsOpts), P, P,
@@ -227,6 +228,20 @@ def fe_gram(V, W, alpha: float = 1.0, C=None, stream=None):
         C = torch.empty((nblk * b, b), dtype=torch.float64, device=V.device)
     _check(lib().fe_gram(_dev_ptr(V), nblk, n * b, _dev_ptr(W), n, b, _dt_of(V), alpha,
                          _dev_ptr(C), _stream(stream)))
+    return C
+
+
+def fe_gram_noalloc(V, W, C, alpha: float = 1.0, stream=None):
+    """C = alpha V^T W into the caller's C ((nblk*b, b) FP64), with the
+    library's static partials array: the C call allocates nothing."""
+    import torch
+    nblk, n, b = V.shape
+    if W.shape != (n, b) or W.dtype != V.dtype:
+        raise FeError(FE_EINVAL, "W must be (n, b) with V's dtype")
+    if C.shape != (nblk * b, b) or C.dtype != torch.float64:
+        raise FeError(FE_EINVAL, "C must be (nblk*b, b) float64")
+    _check(lib().fe_gram_noalloc(_dev_ptr(V), nblk, n * b, _dev_ptr(W), n, b, _dt_of(V), alpha,
+                                 _dev_ptr(C), _stream(stream)))
     return C
 
 
