@@ -48,6 +48,8 @@ def lib():
         L.oracle_spmm.restype = None
         L.oracle_jacobi.argtypes = [ctypes.c_int32, P, P, ctypes.c_double, ctypes.c_int32]
         L.oracle_jacobi.restype = ctypes.c_int32
+        L.oracle_csr_build.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, P, ctypes.c_int32]
+        L.oracle_csr_build.restype = ctypes.c_int64
         L.oracle_max_threads.argtypes = []
         L.oracle_max_threads.restype = ctypes.c_int32
         _lib = L
@@ -58,9 +60,10 @@ def ptr(a: np.ndarray):
     return ctypes.c_void_p(a.ctypes.data)
 
 
-from .csr import csr_from_edges, degrees  # noqa: E402
+from .csr import csr_from_edges, csr_build, degrees  # noqa: E402
 from .ops import (spmm, gram, block_update, col_norms, max_threads, round_bf16,  # noqa: E402
                   spmm_rows_from_edges)
 from .dense_eig import jacobi_eigh  # noqa: E402
 from .rng import philox4x32_10, refill_column  # noqa: E402
 from .krylov_schur import krylov_schur, KSResult, restart_keep, ritz_scale, EPS23  # noqa: E402
+from .certify import certify  # noqa: E402

@@ -13,6 +13,23 @@ from __future__ import annotations
 import numpy as np
 
 
+def csr_build(n: int, src: np.ndarray, dst: np.ndarray, threads: int = 1):
+    """The same CSR as csr_from_edges, built by the C loop (counting, per-row
+    sort and merge), for graphs too large for a global sort of the pairs."""
+    from . import lib, ptr
+    s = np.ascontiguousarray(src, dtype=np.int32)
+    d = np.ascontiguousarray(dst, dtype=np.int32)
+    assert s.shape == d.shape
+    if s.size and (min(s.min(), d.min()) < 0 or max(s.max(), d.max()) >= n):
+        raise ValueError("vertex id out of range")
+    row_ptr = np.empty(n + 1, dtype=np.int64)
+    col = np.empty(max(2 * s.size, 1), dtype=np.int32)
+    nnz = lib().oracle_csr_build(n, s.size, ptr(s), ptr(d), ptr(row_ptr), ptr(col), threads)
+    if nnz < 0:
+        raise MemoryError("oracle_csr_build: allocation failed")
+    return row_ptr, col[:nnz]
+
+
 def csr_from_edges(n: int, src: np.ndarray, dst: np.ndarray):
     s = np.concatenate([np.asarray(src, dtype=np.int64), np.asarray(dst, dtype=np.int64)])
     d = np.concatenate([np.asarray(dst, dtype=np.int64), np.asarray(src, dtype=np.int64)])

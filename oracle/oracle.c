@@ -11,6 +11,13 @@
  *                     threads > 1 only splits rows between OpenMP threads; the
  *                     per-row summation order is unchanged, so the result is
  *                     bitwise identical for every thread count.
+ *   oracle_csr_build -- the pattern CSR of an edge stream by its definition
+ *                     (the sparse matrix format section: no values; symmetric
+ *                     for an undirected graph): every pair (u, v) gives (u, v)
+ *                     and (v, u), self-loops are dropped, each row's columns are
+ *                     sorted ascending and repeats merged.  OpenMP splits the
+ *                     counting and the per-row sorting; the result does not
+ *                     depend on the thread count.
  *   oracle_jacobi  -- cyclic-by-row Jacobi eigenvalue algorithm for a dense
  *                     symmetric matrix (Golub & Van Loan, Matrix Computations,
  *                     the symmetric Jacobi section): the brute-force check of
@@ -38,6 +45,74 @@ void oracle_spmm(int64_t n, const int64_t *row_ptr, const int32_t *col, const do
       for (int32_t c = 0; c < b; ++c) y[c] += x[c];
     }
   }
+}
+
+static int cmp_i32(const void *a, const void *b) {
+  const int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+/* row_ptr: n+1 entries; col: room for 2*m entries.  Returns nnz, or -1 when
+ * the scratch allocation fails. */
+int64_t oracle_csr_build(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                         int64_t *row_ptr, int32_t *col, int32_t threads) {
+  if (threads < 1) threads = 1;
+  int64_t *cnt = calloc((size_t)n + 1, sizeof(int64_t));
+  int32_t *raw = malloc(sizeof(int32_t) * (size_t)(2 * m > 0 ? 2 * m : 1));
+  int64_t *cur = malloc(sizeof(int64_t) * (size_t)(n + 1));
+  if (!cnt || !raw || !cur) {
+    free(cnt);
+    free(raw);
+    free(cur);
+    return -1;
+  }
+#pragma omp parallel for schedule(static) num_threads(threads)
+  for (int64_t e = 0; e < m; ++e) {
+    if (src[e] == dst[e]) continue;
+#pragma omp atomic
+    cnt[src[e]]++;
+#pragma omp atomic
+    cnt[dst[e]]++;
+  }
+  int64_t acc = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    cur[i] = acc;
+    acc += cnt[i];
+  }
+  cur[n] = acc;
+  for (int64_t i = 0; i <= n; ++i) cnt[i] = cur[i]; /* cnt = raw row starts */
+#pragma omp parallel for schedule(static) num_threads(threads)
+  for (int64_t e = 0; e < m; ++e) {
+    const int32_t u = src[e], v = dst[e];
+    if (u == v) continue;
+    int64_t p, q;
+#pragma omp atomic capture
+    p = cur[u]++;
+#pragma omp atomic capture
+    q = cur[v]++;
+    raw[p] = v;
+    raw[q] = u;
+  }
+  /* sort each row, merge repeats; cur[i] = distinct count of row i */
+#pragma omp parallel for schedule(dynamic, 4096) num_threads(threads)
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t *r = raw + cnt[i];
+    const int64_t len = cnt[i + 1] - cnt[i];
+    qsort(r, (size_t)len, sizeof(int32_t), cmp_i32);
+    int64_t k = 0;
+    for (int64_t t = 0; t < len; ++t)
+      if (k == 0 || r[t] != r[k - 1]) r[k++] = r[t];
+    cur[i] = k;
+  }
+  row_ptr[0] = 0;
+  for (int64_t i = 0; i < n; ++i) row_ptr[i + 1] = row_ptr[i] + cur[i];
+#pragma omp parallel for schedule(dynamic, 4096) num_threads(threads)
+  for (int64_t i = 0; i < n; ++i)
+    memcpy(col + row_ptr[i], raw + cnt[i], sizeof(int32_t) * (size_t)cur[i]);
+  free(cnt);
+  free(raw);
+  free(cur);
+  return row_ptr[n];
 }
 
 int32_t oracle_max_threads(void) {

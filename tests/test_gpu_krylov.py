@@ -157,24 +157,30 @@ def test_mixed_precision_bf16_to_fp32(fe):
 
 def test_rmat22_full_size_fp32(fe):
     """R-MAT scale 22 (the benchmark graph), FP32 storage, nev 8, block 4,
-    m 48, tol 1e-6, against an FP64-storage solve of the same graph; the FP32
-    eigenvectors are certified by the oracle's FP64 product: every returned
-    value lies within its explicit residual of an eigenvalue of A, and
-    matches the FP64 solve to 1e-8 relative."""
+    m 48, tol 1e-6, against the oracle's own FP64 eigenvalues of the same
+    graph (tol 1e-10, a committed fixture written by
+    tests/golden/make_golden.py): within 1e-8 relative.  The FP32
+    eigenvectors' residuals are recomputed with the oracle's FP64 product
+    over all rows."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "rmat22_evals.json")) as f:
+        ref = json.load(f)
+    lam = np.array(ref["evals"])
     n, s, d = S.rmat_edges(22, seed=22)
     A = fe.fe_csr_build(n, s, d, fe.FE_GRAPH_DEFAULT | fe.FE_RELABEL_BY_DEGREE)
+    assert A.nnz == ref["nnz"]
     r32 = fe.fe_krylov_schur(A, 8, 4, 48, 1e-6, dtype=torch.float32, seed=1)
-    r64 = fe.fe_krylov_schur(A, 8, 4, 48, 1e-10, dtype=torch.float64, seed=2, want_vectors=False)
-    assert r32.status == fe.FE_OK and r64.status == fe.FE_OK
-    assert np.all(np.abs(r32.evals - r64.evals) <= 1e-8 * np.abs(r64.evals))
+    assert r32.status == fe.FE_OK
+    assert np.all(np.abs(r32.evals - lam) <= 1e-8 * np.abs(lam))
     assert r32.resid.max() <= 1e-6
-    rp, ci = O.csr_from_edges(n, s, d)
+    rp, ci = O.csr_build(n, s, d, threads=16)
     X = r32.evecs.double().cpu().numpy()
     R = O.spmm(rp, ci, X, threads=16) - X * r32.evals
     res = np.linalg.norm(R, axis=0) / np.linalg.norm(X, axis=0)
     # the returned vectors are the FP64 Ritz vectors rounded to FP32, which adds
-    # up to about 2^-24 * ||A|| (||A|| = |lambda_1|) to each residual
-    rounding = 2.0 ** -23 * np.abs(r64.evals).max()
+    # up to 2^-24 (||A|| + |theta|) <= 2^-23 |lambda_1| to each residual
+    rounding = 2.0 ** -23 * np.abs(lam).max()
     assert np.all(res <= 1e-6 * np.abs(r32.evals) + rounding)
 
 

@@ -162,3 +162,39 @@ def test_refills_keep_tight_tolerance(name):
     assert r.converged and r.refills > 0
     assert r.resid.max() <= 1e-12
     assert all(np.min(np.abs(lam - t)) <= 1e-12 * max(1.0, abs(t)) for t in r.evals)
+
+
+# ------------------------------------------------- C CSR build, certificate
+def test_csr_build_matches_definition():
+    n, s, d = S.chung_lu_edges(5000, seed=12)
+    s = np.concatenate([s, s[:700], np.arange(60)])  # repeats and self-loops
+    d = np.concatenate([d, d[:700], np.arange(60)])
+    rp, ci = O.csr_from_edges(n, s, d)
+    for threads in (1, 4):
+        rp2, ci2 = O.csr_build(n, s, d, threads=threads)
+        assert np.array_equal(rp, rp2) and np.array_equal(ci, ci2)
+    for g in (S.star_graph(300), S.complete_graph(30), S.rmat_edges(12, seed=4)):
+        rp, ci = O.csr_from_edges(*g)
+        rp2, ci2 = O.csr_build(*g, threads=3)
+        assert np.array_equal(rp, rp2) and np.array_equal(ci, ci2)
+
+
+def test_certificate_bounds_hold_on_known_spectra():
+    """Path graph P_n (eigenvalues 2 cos(pi k/(n+1)), eigenvectors
+    sin(pi j k/(n+1))): perturbed eigenvectors give Rayleigh quotients whose
+    true errors lie within both the residual bound and the Kato-Temple bound."""
+    n = 400
+    g = S.path_graph(n)
+    rp, ci = O.csr_from_edges(*g)
+    ks = np.array([1, 2, 3, 200])
+    j = np.arange(1, n + 1)[:, None]
+    lam = 2 * np.cos(np.pi * ks / (n + 1))
+    V = np.sin(np.pi * j * ks[None, :] / (n + 1))
+    rng = np.random.default_rng(1)
+    X = V + 1e-6 * rng.standard_normal(V.shape) * np.linalg.norm(V, axis=0) / np.sqrt(n)
+    theta, resid, kt = O.certify(rp, ci, X)
+    err = np.abs(theta - lam)   # the top gaps are ~2e-4, well above the residuals
+    assert np.all(np.isfinite(kt))
+    assert np.all(err <= resid) and np.all(err <= kt) and np.all(kt < resid)
+    theta0, resid0, _ = O.certify(rp, ci, V)   # exact eigenvectors
+    assert np.allclose(theta0, lam, atol=1e-13) and resid0.max() < 1e-13
