@@ -215,6 +215,14 @@ typedef struct {
                             Ignored without a start block.  (A fallback rule for
                             learned start blocks; not in the paper.) */
   double start_drop;     /* 0 -> 10 */
+  void *workspace;       /* NULL: the solve allocates its device memory (hipMalloc) and
+                            frees it before returning.  Otherwise a device buffer of at
+                            least fe_ks_workspace_bytes() bytes, 256-byte aligned, owned
+                            by the caller and used for every device buffer of the solve
+                            (the solve then makes no device allocation; it still uses
+                            a few KB of pinned host memory).  Its contents on entry do
+                            not matter; on return they are undefined. */
+  uint64_t workspace_bytes; /* size of `workspace` */
 } fe_ks_opts;
 
 /* Per-solve report (all times in seconds). */
@@ -239,16 +247,16 @@ typedef struct {
   double t_host, t_total;  /* host small-matrix work; wall clock of the solve */
   int32_t start_fallback;  /* restart at which the caller's start block was abandoned
                               (opts.start_check), -1 if never */
+  int32_t device_allocs;   /* device allocations the solve made (0 with a workspace) */
 } fe_ks_report;
 
 /*
  * Block Krylov-Schur for the nev largest-magnitude eigenpairs of the
  * symmetric pattern matrix A (the paper's selected solver, following its
  * generic eigen-iteration with the block extension).  block = b vectors per
- * step, m = subspace size (m % block == 0, 1 <= nev <= m - block, m <= 128,
- * block in {1,2,4,8,16}, m + block <= n; the
- * restart keeps p = m - block * max(1, (m - nev) / (2 block)) vectors, p <= 64
- * and m * p <= 8192), tol > 0: pair i is converged when its
+ * step, m = subspace size (m % block == 0, 1 <= nev <= m - block, nev <= 64,
+ * m <= 256, block in {1,2,4,8,16}, m + block <= n; the restart keeps
+ * p = m - block * max(1, (m - nev) / (2 block)) vectors, p <= 128), tol > 0: pair i is converged when its
  * Krylov-Schur residual estimate is <= tol * max(eps^(2/3), |theta_i|), eps
  * the FP64 unit roundoff.
  * Final check (FP64 whatever the storage dtype): the Ritz vectors X = V Y are
@@ -258,16 +266,28 @@ typedef struct {
  * descending, ties to the larger theta); evecs (device n x nev in opts->dt,
  * original vertex order, 2-norm 1 up to storage rounding) or NULL; rep (host)
  * or NULL.
- * Workspace: (m + block) * n elements of dt (mixed: of BF16, then from the
- * switch of dt, with n * block doubles during the switch), 2 * nev * n
- * doubles and small FP64 buffers, allocated for the call and freed before
- * return.  Synchronises the stream before returning.
- * Errors: FE_EINVAL, FE_ENOMEM, FE_EDEVICE, FE_ENOCONV (max_restarts reached;
+ * Device memory: (m + block) * n elements of dt (mixed: of BF16, then from
+ * the switch of dt, with n * block doubles during the switch), 2 * nev * n
+ * doubles and small FP64 buffers; allocated for the call and freed before
+ * return, or carved from opts->workspace (fe_ks_workspace_bytes gives the
+ * size).  Synchronises the stream before returning.
+ * Errors: FE_EINVAL (also a workspace smaller than fe_ks_workspace_bytes or
+ * not 256-byte aligned), FE_ENOMEM, FE_EDEVICE, FE_ENOCONV (max_restarts reached;
  * outputs hold the current estimates), FE_EUNSUPPORTED (sizes beyond the limits).
  */
 fe_status fe_krylov_schur(const fe_csr *A, int32_t nev, int32_t block, int32_t m, double tol,
                           const fe_ks_opts *opts, double *evals, void *evecs,
                           fe_ks_report *rep);
+
+/*
+ * Device memory fe_krylov_schur needs for these arguments (the options that
+ * matter: dt, mixed, and whether a start block is given), so that a caller
+ * can pass it as opts->workspace (e.g. a buffer from its own allocator).
+ * Same argument checks as fe_krylov_schur (tol is not checked).
+ * Errors: FE_EINVAL, FE_EUNSUPPORTED.
+ */
+fe_status fe_ks_workspace_bytes(const fe_csr *A, int32_t nev, int32_t block, int32_t m,
+                                const fe_ks_opts *opts, uint64_t *bytes);
 
 /* ------------------------------------------------------------------------
  * Learned start block (not in the paper: a learned warm start for the

@@ -796,23 +796,43 @@ fe_status update_t(void* W, int64_t n, int32_t b, const void* V, int32_t nblk, i
 // operand, alpha Y from LDS padded with zeros to whole 16 x 16 tiles, is
 // indexed the same way).  Sixteen wavefronts per workgroup share the LDS copy
 // of Y.  FP64 arithmetic for every storage type.
-constexpr int kRotMax = 64;    // p (or c_out): at most four 16-column tiles
-constexpr int kRotRows = 128;  // largest m
+// Up to 64 output columns with m16 x p16 <= 64 KB the scaled, zero-padded Y
+// sits in LDS; wider (p up to 128) or taller (m up to 256) products read it
+// from a padded copy in device memory (GY), where the sixteen lanes of each
+// operand read hit the same cache lines.
+constexpr int kRotMax = 128;   // p (or c_out): at most eight 16-column tiles
+constexpr int kRotRows = 256;  // largest m
+constexpr int kRotLdsMax = 64;  // largest p (or c_out) with Y in LDS
 constexpr int kRotWG = 512;
 
-template <typename T, typename TO, int B, int NT>
+// Ypad (m16 x p16) = alpha Y (m x p), zero beyond m and p.
+__global__ void pad_y_kernel(const double* __restrict__ Y, int32_t m, int32_t p, int32_t m16,
+                             int32_t p16, double alpha, double* __restrict__ Ypad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m16 * p16) return;
+  const int t = i / p16, c = i - t * p16;
+  Ypad[i] = (t < m && c < p) ? alpha * Y[t * p + c] : 0.0;
+}
+
+template <typename T, typename TO, int B, int NT, bool GY>
 __global__ __launch_bounds__(kRotWG) void rotate_kernel(TO* Out, int32_t out_mode,  // may alias V
                                                         int32_t c_out, double beta, int64_t n,
                                                         const T* V, int32_t nblk, int64_t stride,
                                                         const double* __restrict__ Y, double alpha,
                                                         int32_t p, int32_t p16, int32_t m16) {
-  extern __shared__ double Ys[];  // m16 x p16: alpha Y, zero beyond m and p
+  extern __shared__ double Ysh[];  // m16 x p16: alpha Y, zero beyond m and p
   const int m = nblk * B;
-  for (int i = threadIdx.x; i < m16 * p16; i += blockDim.x) {
-    const int t = i / p16, c = i - t * p16;
-    Ys[i] = (t < m && c < p) ? alpha * Y[t * p + c] : 0.0;
+  const double* Ys;
+  if constexpr (GY) {
+    Ys = Y;  // already scaled and padded to m16 x p16
+  } else {
+    for (int i = threadIdx.x; i < m16 * p16; i += blockDim.x) {
+      const int t = i / p16, c = i - t * p16;
+      Ysh[i] = (t < m && c < p) ? alpha * Y[t * p + c] : 0.0;
+    }
+    __syncthreads();
+    Ys = Ysh;
   }
-  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int nwave = blockDim.x >> 6;
@@ -881,27 +901,43 @@ __global__ __launch_bounds__(kRotWG) void rotate_kernel(TO* Out, int32_t out_mod
 template <typename T, typename TO = T>
 fe_status rotate_t(void* Out, int32_t out_mode, int32_t c_out, double beta, int64_t n, int32_t b,
                    const void* V, int32_t nblk, int64_t stride, const double* Y, double alpha,
-                   int32_t p, hipStream_t s) {
+                   int32_t p, double* ypad, hipStream_t s) {
   const int m = nblk * b;
   const int p16 = (p + 15) / 16 * 16;
   const int m16 = (m + 15) / 16 * 16;
-  const size_t lds = (size_t)m16 * p16 * sizeof(double);
-  if (p > kRotMax || m > kRotRows || lds > 64 * 1024)
-    return fail(FE_EUNSUPPORTED, "rotate: m=%d (max %d), p=%d (max %d) or m*p too large", m,
-                kRotRows, p, kRotMax);
+  const size_t lds_need = (size_t)m16 * p16 * sizeof(double);
+  if (p > kRotMax || m > kRotRows)
+    return fail(FE_EUNSUPPORTED, "rotate: m=%d (max %d), p=%d (max %d)", m, kRotRows, p, kRotMax);
+  const bool gy = p16 > kRotLdsMax || lds_need > 64 * 1024;
+  if (gy && !ypad)
+    return fail(FE_EUNSUPPORTED, "rotate: m=%d, p=%d needs the padded-Y buffer", m, p);
+  const size_t lds = gy ? 0 : lds_need;
+  const double* Yk = Y;
+  double a = alpha;
+  if (gy) {
+    const int cnt = m16 * p16;
+    hipLaunchKernelGGL(pad_y_kernel, dim3((cnt + 255) / 256), dim3(256), 0, s, Y, m, p, m16, p16,
+                       alpha, ypad);
+    FE_HIP(hipGetLastError());
+    Yk = ypad;
+    a = 1.0;
+  }
   const int64_t groups = (n + 15) / 16;
   const int wpg = kRotWG / 64;
   const uint32_t grid = (uint32_t)std::max<int64_t>(1, std::min<int64_t>((groups + wpg - 1) / wpg, 2048));
   TO* O = static_cast<TO*>(Out);
   const T* Vp = static_cast<const T*>(V);
-#define FE_ROT(BB, NTT)                                                                          \
-  if (b == BB && p16 == 16 * NTT) {                                                              \
-    hipLaunchKernelGGL((rotate_kernel<T, TO, BB, NTT>), dim3(grid), dim3(kRotWG), lds, s, O,     \
-                       out_mode, c_out, beta, n, Vp, nblk, stride, Y, alpha, p, p16, m16);      \
-    FE_HIP(hipGetLastError());                                                                   \
-    return FE_OK;                                                                                \
+#define FE_ROT(BB, NTT, G)                                                                        \
+  if (b == BB && p16 == 16 * NTT && gy == G) {                                                    \
+    hipLaunchKernelGGL((rotate_kernel<T, TO, BB, NTT, G>), dim3(grid), dim3(kRotWG), lds, s, O,   \
+                       out_mode, c_out, beta, n, Vp, nblk, stride, Yk, a, p, p16, m16);          \
+    FE_HIP(hipGetLastError());                                                                    \
+    return FE_OK;                                                                                 \
   }
-#define FE_ROT_B(BB) FE_ROT(BB, 1) FE_ROT(BB, 2) FE_ROT(BB, 3) FE_ROT(BB, 4)
+#define FE_ROT_B(BB)                                                                              \
+  FE_ROT(BB, 1, false) FE_ROT(BB, 2, false) FE_ROT(BB, 3, false) FE_ROT(BB, 4, false)             \
+  FE_ROT(BB, 1, true) FE_ROT(BB, 2, true) FE_ROT(BB, 3, true) FE_ROT(BB, 4, true)                 \
+  FE_ROT(BB, 5, true) FE_ROT(BB, 6, true) FE_ROT(BB, 7, true) FE_ROT(BB, 8, true)
   FE_ROT_B(1) FE_ROT_B(2) FE_ROT_B(4) FE_ROT_B(8) FE_ROT_B(16)
 #undef FE_ROT_B
 #undef FE_ROT
@@ -1048,6 +1084,10 @@ fe_status convert_from(void* dst, fe_dtype ddt, const S* src, int64_t count, hip
 
 }  // namespace
 
+size_t rotate_pad_doubles(int32_t m, int32_t p) {
+  return (size_t)((m + 15) / 16 * 16) * (size_t)((p + 15) / 16 * 16);
+}
+
 // ------------------------------------------------------------- launchers
 size_t gram_partials_doubles(int64_t n, int32_t k, int32_t b) {
   return (size_t)std::max(gram_sets(n), ug_sets(n)) * (size_t)k * (size_t)b;
@@ -1134,33 +1174,33 @@ fe_status update_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nb
 }
 
 fe_status rotate_launch(void* V, int64_t n, int32_t b, int32_t nblk_in, int32_t nblk_out,
-                        int64_t stride, const double* Y, fe_dtype dt, hipStream_t s) {
+                        int64_t stride, const double* Y, double* ypad, fe_dtype dt, hipStream_t s) {
   const int32_t p = nblk_out * b;
   switch (dt) {
-    case FE_F64: return rotate_t<double>(V, 0, 0, 0.0, n, b, V, nblk_in, stride, Y, 1.0, p, s);
-    case FE_F32: return rotate_t<float>(V, 0, 0, 0.0, n, b, V, nblk_in, stride, Y, 1.0, p, s);
-    case FE_BF16: return rotate_t<bf16_t>(V, 0, 0, 0.0, n, b, V, nblk_in, stride, Y, 1.0, p, s);
+    case FE_F64: return rotate_t<double>(V, 0, 0, 0.0, n, b, V, nblk_in, stride, Y, 1.0, p, ypad, s);
+    case FE_F32: return rotate_t<float>(V, 0, 0, 0.0, n, b, V, nblk_in, stride, Y, 1.0, p, ypad, s);
+    case FE_BF16: return rotate_t<bf16_t>(V, 0, 0, 0.0, n, b, V, nblk_in, stride, Y, 1.0, p, ypad, s);
   }
   return fail(FE_EINVAL, "rotate: bad dtype");
 }
 
 fe_status combine_launch(double* Out, int32_t c, int64_t n, int32_t b, const void* V, int32_t nblk,
-                         int64_t stride, const double* Y, fe_dtype dt, hipStream_t s) {
+                         int64_t stride, const double* Y, double* ypad, fe_dtype dt, hipStream_t s) {
   switch (dt) {
-    case FE_F64: return rotate_t<double, double>(Out, 1, c, 0.0, n, b, V, nblk, stride, Y, 1.0, c, s);
-    case FE_F32: return rotate_t<float, double>(Out, 1, c, 0.0, n, b, V, nblk, stride, Y, 1.0, c, s);
-    case FE_BF16: return rotate_t<bf16_t, double>(Out, 1, c, 0.0, n, b, V, nblk, stride, Y, 1.0, c, s);
+    case FE_F64: return rotate_t<double, double>(Out, 1, c, 0.0, n, b, V, nblk, stride, Y, 1.0, c, ypad, s);
+    case FE_F32: return rotate_t<float, double>(Out, 1, c, 0.0, n, b, V, nblk, stride, Y, 1.0, c, ypad, s);
+    case FE_BF16: return rotate_t<bf16_t, double>(Out, 1, c, 0.0, n, b, V, nblk, stride, Y, 1.0, c, ypad, s);
   }
   return fail(FE_EINVAL, "combine: bad dtype");
 }
 
 fe_status mult_update_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk,
                              int64_t stride, const double* C, double alpha, double beta,
-                             fe_dtype dt, hipStream_t s) {
+                             double* ypad, fe_dtype dt, hipStream_t s) {
   switch (dt) {
-    case FE_F64: return rotate_t<double>(W, 1, b, beta, n, b, V, nblk, stride, C, alpha, b, s);
-    case FE_F32: return rotate_t<float>(W, 1, b, beta, n, b, V, nblk, stride, C, alpha, b, s);
-    case FE_BF16: return rotate_t<bf16_t>(W, 1, b, beta, n, b, V, nblk, stride, C, alpha, b, s);
+    case FE_F64: return rotate_t<double>(W, 1, b, beta, n, b, V, nblk, stride, C, alpha, b, ypad, s);
+    case FE_F32: return rotate_t<float>(W, 1, b, beta, n, b, V, nblk, stride, C, alpha, b, ypad, s);
+    case FE_BF16: return rotate_t<bf16_t>(W, 1, b, beta, n, b, V, nblk, stride, C, alpha, b, ypad, s);
   }
   return fail(FE_EINVAL, "update: bad dtype");
 }

@@ -107,18 +107,24 @@ fe_status cgs_mid_launch(void* W, int64_t n, const void* V, int32_t nblk_v, int6
 fe_status update_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk,
                         int64_t blk_stride, const double* C, double alpha, double beta,
                         fe_dtype dt, hipStream_t s);
+// The contractions below (m <= 256 input columns, p <= 128 outputs) keep Y in
+// LDS up to 64 outputs and m16 x p16 <= 64 KB; beyond that they need `ypad`,
+// a device buffer of rotate_pad_doubles(m, p) doubles (else FE_EUNSUPPORTED).
+size_t rotate_pad_doubles(int32_t m, int32_t p);
 // V[:, 0:p] <- V[:, 0:m] * Y[:, 0:p] in place (Y: device FP64, m x p row-major)
 fe_status rotate_launch(void* V, int64_t n, int32_t b, int32_t nblk_in, int32_t nblk_out,
-                        int64_t blk_stride, const double* Y, fe_dtype dt, hipStream_t s);
+                        int64_t blk_stride, const double* Y, double* ypad, fe_dtype dt,
+                        hipStream_t s);
 // W <- beta W + alpha V[:, 0:k] C on the MFMA contraction of the restart
 // (C: device FP64, k x b row-major; W (n x b) may be V's own single block).
 // Same result as update_launch up to the order of the FP64 sums.
 fe_status mult_update_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk,
                              int64_t blk_stride, const double* C, double alpha, double beta,
-                             fe_dtype dt, hipStream_t s);
+                             double* ypad, fe_dtype dt, hipStream_t s);
 // Out (n x c packed, FP64) <- V[:, 0:m] * Y (m x c), V as blocks in dt.
 fe_status combine_launch(double* Out, int32_t c, int64_t n, int32_t b, const void* V, int32_t nblk,
-                         int64_t blk_stride, const double* Y, fe_dtype dt, hipStream_t s);
+                         int64_t blk_stride, const double* Y, double* ypad, fe_dtype dt,
+                         hipStream_t s);
 // FP64 X, AX (n x c): sums[3i] = x_i.ax_i, sums[3i+1] = x_i.x_i,
 // sums[3i+2] = ||ax_i - theta_i x_i||^2
 size_t resid_partials_doubles(int64_t n, int32_t c);

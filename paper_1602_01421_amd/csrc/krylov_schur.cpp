@@ -89,12 +89,20 @@ struct Prof {
   ~Prof() { flush(); }
 };
 
+// Every device buffer of a solve, in 256-byte units: from hipMalloc (freed
+// when the solve returns), or carved in order from a caller's workspace.
+static size_t ws_round(size_t bytes) { return (std::max<size_t>(bytes, 256) + 255) / 256 * 256; }
+
 struct DevBuf {
   std::vector<void*> ptrs;
+  char* arena = nullptr;
+  size_t arena_bytes = 0, arena_used = 0;
+  int allocs = 0;  // hipMalloc calls made
   ~DevBuf() {
     for (void* p : ptrs) hipFree(p);
   }
   void release(void* p) {
+    if (arena) return;
     for (auto& q : ptrs)
       if (q == p) {
         (void)hipFree(q);
@@ -102,13 +110,45 @@ struct DevBuf {
       }
   }
   fe_status get(void** p, size_t bytes) {
-    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
+    const size_t sz = ws_round(bytes);
+    if (arena) {
+      if (arena_used + sz > arena_bytes)
+        return fail(FE_ENOMEM, "fe_krylov_schur: workspace of %zu bytes is too small",
+                    arena_bytes);
+      *p = arena + arena_used;
+      arena_used += sz;
+      return FE_OK;
+    }
+    hipError_t e = hipMalloc(p, sz);
     if (e != hipSuccess)
       return fail(FE_ENOMEM, "fe_krylov_schur: hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    ++allocs;
     ptrs.push_back(*p);
     return FE_OK;
   }
 };
+
+// The sum of every DevBuf::get of a solve (the order does not matter to the
+// bump allocation): setup(), the mixed start block and switch, the final check.
+static size_t ks_workspace_plan(int64_t n, int nev, int b, int m, fe_dtype dt, bool mixed,
+                                bool start) {
+  const fe_dtype dt0 = mixed ? FE_BF16 : dt;
+  const size_t es0 = dtype_size(dt0), esf = dtype_size(dt);
+  const size_t nblk = (size_t)(m / b + 1), kmax = (size_t)(m + b), stride = (size_t)n * b;
+  const size_t d = sizeof(double);
+  size_t t = ws_round(nblk * stride * es0);
+  t += ws_round(d * 2 * kmax * b) + ws_round(d * b * b) + ws_round(d * m * m);
+  t += ws_round(d * rotate_pad_doubles(m + b, std::max(m, 64)));
+  t += ws_round(d * 64) + ws_round(d * 3 * 64);
+  t += ws_round(d * gram_partials_doubles(n, (int32_t)kmax, b));
+  t += ws_round(d * resid_partials_doubles(n, 64));
+  t += ws_round(d * ((size_t)m * b + (size_t)b * b + 1) * nblk);
+  t += ws_round(d * b * b);
+  if (mixed && start) t += ws_round(stride * esf);
+  if (mixed) t += ws_round(nblk * stride * esf) + ws_round(d * stride);
+  t += 2 * ws_round(d * (size_t)n * nev);
+  return t;
+}
 
 struct HostBuf {
   std::vector<void*> ptrs;
@@ -151,7 +191,8 @@ class Solver {
   int switch_restart = -1, spmm_low = 0;
   int64_t n, stride;
   char* V = nullptr;  // m/b + 1 blocks
-  double *dC = nullptr, *dM = nullptr, *dY = nullptr, *dTheta = nullptr, *dSums = nullptr;
+  double *dC = nullptr, *dM = nullptr, *dY = nullptr, *dYpad = nullptr, *dTheta = nullptr,
+         *dSums = nullptr;
   double *dPart = nullptr, *dPartRes = nullptr;
   double *hC1 = nullptr, *hC2 = nullptr, *hG = nullptr, *hM = nullptr, *hY = nullptr,
          *hSums = nullptr, *hTheta = nullptr;
@@ -181,6 +222,10 @@ class Solver {
     set_eta();
     prof.on = o.profile != 0;
     prof.s = s;
+    if (o.workspace) {
+      dev.arena = static_cast<char*>(o.workspace);
+      dev.arena_bytes = o.workspace_bytes;
+    }
   }
 
   // eta: refill threshold on the column-wise ratio (reading: 1e-10 for FP64
@@ -220,7 +265,7 @@ class Solver {
     FE_TRY(dev.get((void**)&V2, (size_t)nblk * stride * es2));
     FE_TRY(dev.get((void**)&tmp, (size_t)n * b * sizeof(double)));
     prof.begin(P_OTHER);
-    FE_TRY(combine_launch(tmp, b, n, b, V, m / b, stride, dY, dt, s));
+    FE_TRY(combine_launch(tmp, b, n, b, V, m / b, stride, dY, dYpad, dt, s));
     FE_TRY(convert_launch(V2, dt_final, tmp, FE_F64, (int64_t)n * b, s));
     prof.end();
     FE_TRY(sync());
@@ -240,6 +285,7 @@ class Solver {
     FE_TRY(dev.get((void**)&dC, sizeof(double) * 2 * kmax * b));
     FE_TRY(dev.get((void**)&dM, sizeof(double) * b * b));
     FE_TRY(dev.get((void**)&dY, sizeof(double) * m * m));
+    FE_TRY(dev.get((void**)&dYpad, sizeof(double) * rotate_pad_doubles(m + b, std::max(m, 64))));
     FE_TRY(dev.get((void**)&dTheta, sizeof(double) * 64));
     FE_TRY(dev.get((void**)&dSums, sizeof(double) * 3 * 64));
     FE_TRY(dev.get((void**)&dPart, sizeof(double) * gram_partials_doubles(n, kmax, b)));
@@ -278,7 +324,7 @@ class Solver {
   // kernel's 2 k b FP64 FMAs per row make it VALU bound there.
   fe_status update(void* W, const void* Vp, int nblk, const double* C, double alpha, double beta) {
     prof.begin(P_UPDATE);
-    fe_status st = b >= 8 ? mult_update_launch(W, n, b, Vp, nblk, stride, C, alpha, beta, dt, s)
+    fe_status st = b >= 8 ? mult_update_launch(W, n, b, Vp, nblk, stride, C, alpha, beta, dYpad, dt, s)
                           : update_launch(W, n, b, Vp, nblk, stride, C, alpha, beta, dt, s);
     prof.end();
     ++update_calls;
@@ -729,7 +775,7 @@ class Solver {
         for (int j = 0; j < p; ++j) hY[(size_t)i * p + j] = Y[(size_t)i * m + j];
       FE_HIP(hipMemcpyAsync(dY, hY, sizeof(double) * m * p, hipMemcpyHostToDevice, s));
       prof.begin(P_OTHER);
-      FE_TRY(rotate_launch(V, n, b, m / b, p / b, stride, dY, dt, s));
+      FE_TRY(rotate_launch(V, n, b, m / b, p / b, stride, dY, dYpad, dt, s));
       FE_TRY(copy_block(blk(p / b), blk(m / b), n, b, dt, s));
       prof.end();
       std::vector<double> Bn((size_t)b * m, 0.0);
@@ -757,7 +803,7 @@ class Solver {
     FE_HIP(hipMemcpyAsync(dY, hY, sizeof(double) * m * nev, hipMemcpyHostToDevice, s));
     FE_HIP(hipMemcpyAsync(dTheta, hTheta, sizeof(double) * nev, hipMemcpyHostToDevice, s));
     prof.begin(P_OTHER);
-    FE_TRY(combine_launch(X, nev, n, b, V, m / b, stride, dY, dt, s));
+    FE_TRY(combine_launch(X, nev, n, b, V, m / b, stride, dY, dYpad, dt, s));
     prof.end();
     prof.begin(P_OTHER);
     FE_TRY(spmm_launch(A, X, AX, nev, FE_F64, s));
@@ -794,6 +840,7 @@ class Solver {
       rep->switch_restart = switch_restart;
       rep->spmm_calls_low = spmm_low;
       rep->start_fallback = start_fallback;
+      rep->device_allocs = dev.allocs;
       for (int j = 0; j < nev; ++j) {
         rep->rho[j] = rho[j];
         rep->ritz[j] = theta[j];
@@ -817,6 +864,41 @@ class Solver {
 }  // namespace
 }  // namespace fe
 
+namespace {
+fe_status ks_check(const fe::Csr* A, int32_t nev, int32_t block, int32_t m, double tol,
+                   const fe_ks_opts& o) {
+  using namespace fe;
+  if (!A) return fail(FE_EINVAL, "fe_krylov_schur: NULL argument");
+  if (!dtype_ok(o.dt)) return fail(FE_EINVAL, "fe_krylov_schur: bad dtype");
+  if (block < 1 || block > 16 || m < 1 || m % block || nev < 1 || nev > m - block || !(tol > 0))
+    return fail(FE_EINVAL, "fe_krylov_schur: need 1<=block<=16, m %% block == 0, 1<=nev<=m-block, tol>0");
+  if (o.which != 0) return fail(FE_EUNSUPPORTED, "fe_krylov_schur: only largest magnitude");
+  const int p = m - block * std::max(1, (m - nev) / (2 * block));
+  if (m > 256 || p > 128 || nev > 64)
+    return fail(FE_EUNSUPPORTED, "fe_krylov_schur: m=%d keeps p=%d (limits m<=256, p<=128, nev<=64)", m, p);
+  if (block != 1 && block != 2 && block != 4 && block != 8 && block != 16)
+    return fail(FE_EUNSUPPORTED, "fe_krylov_schur: block must be 1, 2, 4, 8 or 16");
+  if ((int64_t)m + block > A->n) return fail(FE_EINVAL, "fe_krylov_schur: m + block > n");
+  if (o.workspace && reinterpret_cast<uintptr_t>(o.workspace) % 256)
+    return fail(FE_EINVAL, "fe_krylov_schur: workspace not 256-byte aligned");
+  return FE_OK;
+}
+}  // namespace
+
+extern "C" fe_status fe_ks_workspace_bytes(const fe_csr* A, int32_t nev, int32_t block, int32_t m,
+                                           const fe_ks_opts* opts, uint64_t* bytes) {
+  using namespace fe;
+  if (!bytes) return fail(FE_EINVAL, "fe_ks_workspace_bytes: NULL argument");
+  fe_ks_opts o;
+  std::memset(&o, 0, sizeof o);
+  if (opts) o = *opts;
+  o.workspace = nullptr;
+  FE_TRY(ks_check(A, nev, block, m, 1.0, o));
+  const bool mixed = o.mixed != 0 && o.dt != FE_BF16;
+  *bytes = ks_workspace_plan(A->n, nev, block, m, o.dt, mixed, o.start != nullptr);
+  return FE_OK;
+}
+
 extern "C" fe_status fe_krylov_schur(const fe_csr* A, int32_t nev, int32_t block, int32_t m,
                                      double tol, const fe_ks_opts* opts, double* evals,
                                      void* evecs, fe_ks_report* rep) {
@@ -825,16 +907,14 @@ extern "C" fe_status fe_krylov_schur(const fe_csr* A, int32_t nev, int32_t block
   fe_ks_opts o;
   std::memset(&o, 0, sizeof o);
   if (opts) o = *opts;
-  if (!dtype_ok(o.dt)) return fail(FE_EINVAL, "fe_krylov_schur: bad dtype");
-  if (block < 1 || block > 16 || m < 1 || m % block || nev < 1 || nev > m - block || !(tol > 0))
-    return fail(FE_EINVAL, "fe_krylov_schur: need 1<=block<=16, m %% block == 0, 1<=nev<=m-block, tol>0");
-  if (o.which != 0) return fail(FE_EUNSUPPORTED, "fe_krylov_schur: only largest magnitude");
-  const int p = m - block * std::max(1, (m - nev) / (2 * block));
-  if (m > 128 || p > 64 || nev > 64 || (size_t)m * p * 8 > 64 * 1024)
-    return fail(FE_EUNSUPPORTED, "fe_krylov_schur: m=%d keeps p=%d (limits m<=128, p<=64)", m, p);
-  if (block != 1 && block != 2 && block != 4 && block != 8 && block != 16)
-    return fail(FE_EUNSUPPORTED, "fe_krylov_schur: block must be 1, 2, 4, 8 or 16");
-  if ((int64_t)m + block > A->n) return fail(FE_EINVAL, "fe_krylov_schur: m + block > n");
+  FE_TRY(ks_check(A, nev, block, m, tol, o));
+  if (o.workspace) {
+    const bool mixed = o.mixed != 0 && o.dt != FE_BF16;
+    const size_t need = ks_workspace_plan(A->n, nev, block, m, o.dt, mixed, o.start != nullptr);
+    if (o.workspace_bytes < need)
+      return fail(FE_EINVAL, "fe_krylov_schur: workspace of %llu bytes, needs %zu",
+                  (unsigned long long)o.workspace_bytes, need);
+  }
   clear_error();
   Solver S(*A, nev, block, m, tol, o);
   return S.run(evals, evecs, rep);

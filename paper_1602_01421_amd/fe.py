@@ -23,7 +23,8 @@ FE_GRAPH_DEFAULT = FE_SYMMETRIZE | FE_DEDUPE | FE_DROP_SELF
 
 EXPORTED = ("fe_last_error", "fe_version", "fe_csr_build", "fe_csr_from_csr", "fe_csr_info",
             "fe_csr_perm", "fe_csr_export", "fe_csr_free", "fe_spmm", "fe_gram", "fe_gram_noalloc",
-            "fe_block_update", "fe_block_update_gram", "fe_krylov_schur", "fe_dense_symeig", "fe_gnn_param_count",
+            "fe_block_update", "fe_block_update_gram", "fe_krylov_schur", "fe_ks_workspace_bytes",
+            "fe_dense_symeig", "fe_gnn_param_count",
             "fe_gnn_create", "fe_gnn_free", "fe_gnn_get_params", "fe_gnn_set_params",
             "fe_gnn_forward", "fe_gnn_backward", "fe_gnn_adam")
 
@@ -41,7 +42,8 @@ class KsOpts(ctypes.Structure):
                 ("eta", ctypes.c_double), ("profile", ctypes.c_int32),
                 ("verbose", ctypes.c_int32), ("mixed", ctypes.c_int32),
                 ("mixed_switch", ctypes.c_double), ("start_check", ctypes.c_int32),
-                ("start_drop", ctypes.c_double)]
+                ("start_drop", ctypes.c_double), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_uint64)]
 
 
 class KsReport(ctypes.Structure):
@@ -57,7 +59,7 @@ class KsReport(ctypes.Structure):
                 ("bytes_spmm", ctypes.c_double), ("bytes_gram", ctypes.c_double),
                 ("bytes_update", ctypes.c_double),
                 ("t_host", ctypes.c_double), ("t_total", ctypes.c_double),
-                ("start_fallback", ctypes.c_int32)]
+                ("start_fallback", ctypes.c_int32), ("device_allocs", ctypes.c_int32)]
 
 
 _lib = None
@@ -88,6 +90,8 @@ def lib():
             "fe_krylov_schur": [P, i32, i32, i32, f64, ctypes.POINTER(KsOpts), P, P,
                                 ctypes.POINTER(KsReport)],
             "fe_dense_symeig": [i32, P, P, P],
+            "fe_ks_workspace_bytes": [P, i32, i32, i32, ctypes.POINTER(KsOpts),
+                                      ctypes.POINTER(ctypes.c_uint64)],
             "fe_gnn_create": [ctypes.c_uint64, i32, ctypes.POINTER(P)],
             "fe_gnn_get_params": [P, P],
             "fe_gnn_set_params": [P, P],
@@ -304,6 +308,28 @@ class KsResult:
     t_host: float
     t_total: float
     start_fallback: int = -1
+    device_allocs: int = 0
+
+
+def _ks_opts(dtype, mixed, start):
+    import torch
+    if dtype is None:
+        dtype = torch.float64
+    o = KsOpts()
+    o.dt = {torch.float64: FE_F64, torch.float32: FE_F32, torch.bfloat16: FE_BF16}[dtype]
+    o.mixed = int(mixed)
+    if start is not None:
+        o.start = _dev_ptr(start).value
+    return o, dtype
+
+
+def fe_ks_workspace_bytes(A: Csr, nev: int, block: int, m: int, dtype=None, mixed: bool = False,
+                          start=None) -> int:
+    """Device bytes fe_krylov_schur needs for these arguments (its workspace)."""
+    o, _ = _ks_opts(dtype, mixed, start)
+    out = ctypes.c_uint64()
+    _check(lib().fe_ks_workspace_bytes(A.handle, nev, block, m, ctypes.byref(o), ctypes.byref(out)))
+    return out.value
 
 
 def fe_krylov_schur(A: Csr, nev: int, block: int, m: int, tol: float, dtype=None, start=None,
@@ -311,8 +337,9 @@ def fe_krylov_schur(A: Csr, nev: int, block: int, m: int, tol: float, dtype=None
                     want_vectors: bool = True, profile: bool = False,
                     verbose: bool = False, mixed: bool = False,
                     mixed_switch: float = 0.0, start_check: int = 0,
-                    start_drop: float = 0.0) -> KsResult:
-    """Block Krylov-Schur for the nev largest-magnitude eigenpairs (see fe.h)."""
+                    start_drop: float = 0.0, workspace=None) -> KsResult:
+    """Block Krylov-Schur for the nev largest-magnitude eigenpairs (see fe.h).
+    workspace: optional device tensor of at least fe_ks_workspace_bytes bytes."""
     import torch
     if dtype is None:
         dtype = torch.float64
@@ -334,6 +361,9 @@ def fe_krylov_schur(A: Csr, nev: int, block: int, m: int, tol: float, dtype=None
         if start.shape != (A.n, block) or start.dtype != dtype:
             raise FeError(FE_EINVAL, "start must be (n, block) in the solve dtype")
         o.start = _dev_ptr(start).value
+    if workspace is not None:
+        o.workspace = _dev_ptr(workspace).value
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
     evals = np.zeros(nev, dtype=np.float64)
     evecs = torch.empty((A.n, nev), dtype=dtype, device="cuda") if want_vectors else None
     rep = KsReport()
@@ -350,7 +380,8 @@ def fe_krylov_schur(A: Csr, nev: int, block: int, m: int, tol: float, dtype=None
                     t_update=rep.t_update, t_other_dev=rep.t_other_dev,
                     bytes_spmm=rep.bytes_spmm, bytes_gram=rep.bytes_gram,
                     bytes_update=rep.bytes_update, t_host=rep.t_host,
-                    t_total=rep.t_total, start_fallback=rep.start_fallback)
+                    t_total=rep.t_total, start_fallback=rep.start_fallback,
+                    device_allocs=rep.device_allocs)
 
 
 def fe_dense_symeig(a: np.ndarray):

@@ -233,10 +233,44 @@ def test_wide_block_large_subspace_fp32(fe):
 def test_subspace_limits(fe):
     g = S.rmat_edges(12, seed=1)
     A, rp, ci = setup(fe, g)
-    for args in [(8, 8, 128), (8, 16, 144)]:  # keeps p = 72 > 64; m > 128
+    for args in [(32, 8, 256), (8, 16, 272), (65, 16, 96)]:  # p = 144 > 128; m > 256; nev > 64
         with pytest.raises(fe.FeError) as e:
             fe.fe_krylov_schur(A, *args, 1e-8, dtype=torch.float32)
         assert e.value.status == fe.FE_EUNSUPPORTED
+
+
+# ------------------------------------------- many-eigenvalue regime (nev 32)
+@pytest.mark.parametrize("b,m", [(4, 128), (8, 192)])
+def test_many_eigenvalues_fp64_matches_oracle(fe, b, m):
+    """nev = 32 (the paper's many-eigenvalue runs), block 4 / m 128 (keeps
+    p = 80 Ritz vectors) and block 8 / m 192 (p = 112): the restart and the
+    final Ritz vectors need more than 64 output columns or more than 128
+    basis columns, so the contraction reads its coefficients from a padded
+    copy in device memory.  FP64 storage: same products and eigenvalues
+    (1e-10) as the oracle from the same start block."""
+    g = S.chung_lu_edges(20000, alpha=2.2, mean_deg=12, seed=31)
+    A, rp, ci = setup(fe, g)
+    X0 = S.normal((A.n, b), seed=7)
+    ref = oracle_ks(rp, ci, A.n, 32, b, m, 1e-10, X0)
+    r = fe.fe_krylov_schur(A, 32, b, m, 1e-10, dtype=torch.float64,
+                           start=torch.tensor(X0, device="cuda"))
+    assert r.status == fe.FE_OK and ref.converged
+    assert np.allclose(r.evals, ref.evals, rtol=1e-10, atol=0)
+    assert r.spmm_calls == ref.spmm_calls and r.restarts == ref.restarts
+    check_vectors(rp, ci, r)
+
+
+def test_many_eigenvalues_fp32(fe):
+    g = S.rmat_edges(14, seed=14)
+    A, rp, ci = setup(fe, g)
+    X0 = S.normal((A.n, 4), seed=3)
+    ref = oracle_ks(rp, ci, A.n, 32, 4, 128, 1e-12, X0)
+    r = fe.fe_krylov_schur(A, 32, 4, 128, 1e-6, dtype=torch.float32,
+                           start=torch.tensor(X0, dtype=torch.float32, device="cuda"))
+    assert r.status == fe.FE_OK
+    assert np.all(np.abs(r.evals - ref.evals) <= 1e-8 * np.abs(ref.evals))
+    assert r.resid.max() <= 1e-6
+    check_vectors(rp, ci, r)
 
 
 def test_start_block_with_nan_and_repeated_columns(fe):
@@ -323,3 +357,31 @@ def test_start_check_kept_start_changes_nothing(fe):
     assert mx.status == fe.FE_OK and mx.start_fallback == 2
     assert np.all(np.abs(mx.evals - rnd.evals) <= 1e-8 * np.abs(rnd.evals))
     assert mx.resid.max() <= 1e-6
+
+
+# ------------------------------------------------- caller-owned workspace
+@pytest.mark.parametrize("dtype,mixed,with_start", [(torch.float64, False, True),
+                                                    (torch.float32, True, True),
+                                                    (torch.float32, False, False)])
+def test_workspace_makes_no_device_allocation(fe, dtype, mixed, with_start):
+    """A torch buffer of fe_ks_workspace_bytes bytes passed as the solve's
+    workspace: the library makes no device allocation during the call (mixed
+    storage included, whose switch needs a second subspace), and the result is
+    bitwise the result of a solve that allocates its own memory."""
+    g = S.chung_lu_edges(30000, alpha=2.2, mean_deg=12, seed=41)
+    A, rp, ci = setup(fe, g)
+    start = torch.tensor(S.normal((A.n, 4), seed=5), device="cuda").to(dtype) if with_start else None
+    kw = dict(dtype=dtype, mixed=mixed, start=start, seed=3)
+    r1 = fe.fe_krylov_schur(A, 8, 4, 48, 1e-6, **kw)
+    nbytes = fe.fe_ks_workspace_bytes(A, 8, 4, 48, dtype=dtype, mixed=mixed, start=start)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    r2 = fe.fe_krylov_schur(A, 8, 4, 48, 1e-6, workspace=ws, **kw)
+    assert r1.status == fe.FE_OK and r2.status == fe.FE_OK
+    assert r1.device_allocs > 0 and r2.device_allocs == 0
+    assert np.array_equal(r1.evals, r2.evals) and r1.spmm_calls == r2.spmm_calls
+    assert torch.equal(r1.evecs, r2.evecs)
+    if mixed:
+        assert r2.switch_restart >= 0
+    with pytest.raises(fe.FeError) as e:
+        fe.fe_krylov_schur(A, 8, 4, 48, 1e-6, workspace=ws[: nbytes - 256], **kw)
+    assert e.value.status == fe.FE_EINVAL
