@@ -173,8 +173,12 @@ fe_status fe_block_update(void *W, int64_t n, int32_t b, const void *V, int32_t 
  *                            b rows W^T W)
  * Equal to fe_block_update (alpha -1, beta 1) followed by fe_gram over the
  * nblk blocks plus W, up to the order of the FP64 sums.  V and W as in
- * fe_gram; W must not overlap V.  Errors: FE_EINVAL (sizes, NULL, overlap),
- * FE_EUNSUPPORTED (b not in {1,2,4,8,16} or k > 64), FE_ENOMEM, FE_EDEVICE.
+ * fe_gram; W must not overlap V.  At b = 4 and b = 16 with k + b <= 128 the
+ * solver's register-resident kernels run (W, V and the block stride then
+ * aligned to min(16, 4 x element size) bytes); otherwise an LDS-tiled kernel
+ * with k <= 64.
+ * Errors: FE_EINVAL (sizes, NULL, overlap, alignment), FE_EUNSUPPORTED (b not
+ * in {1,2,4,8,16}, or k beyond those limits), FE_ENOMEM, FE_EDEVICE.
  */
 fe_status fe_block_update_gram(void *W, int64_t n, int32_t b, const void *V, int32_t nblk,
                                int64_t blk_stride, const double *C, double *Cout, fe_dtype dt,
@@ -356,7 +360,7 @@ fe_status fe_gnn_adam(fe_gnn *g, double lr, double clip, void *hip_stream);
  * projected problem of the eigen-iteration, which the paper solves with
  * LAPACK-class code).  a: host n x n row-major (read only); w: host n
  * eigenvalues, unordered; z: host n x n row-major, column j the unit
- * eigenvector of w[j].  Householder tridiagonalisation + implicit-shift QL.
+ * eigenvector of w[j].  Householder tridiagonalisation + implicit-shift QR.
  * Errors: FE_EINVAL (n < 1, NULL), FE_ENOCONV (QL iteration limit).
  */
 fe_status fe_dense_symeig(int32_t n, const double *a, double *w, double *z);

@@ -416,19 +416,26 @@ fe_status fe_block_update_gram(void* W, int64_t n, int32_t b, const void* V, int
                                void* stream) {
   FE_TRY(check_blocks("fe_block_update_gram", V, nblk, stride, n, b, dt));
   if (!W || !C || !Cout) return fail(FE_EINVAL, "fe_block_update_gram: NULL argument");
-  if (!(b == 1 || b == 2 || b == 4 || b == 8 || b == 16) || nblk * b > 64)
-    return fail(FE_EUNSUPPORTED, "fe_block_update_gram: needs b in {1,2,4,8,16} and k <= 64");
+  const bool fused = cgs_mid_supported(b, nblk);
+  if (!fused && (!(b == 1 || b == 2 || b == 4 || b == 8 || b == 16) || nblk * b > 64))
+    return fail(FE_EUNSUPPORTED,
+                "fe_block_update_gram: needs b in {1,2,4,8,16} and k <= 64 (k + b <= 128 at b = 4, 16)");
   const size_t es = dtype_size(dt);
   const size_t vbytes = ((size_t)(nblk - 1) * stride + (size_t)n * b) * es;
   if (overlap(W, (size_t)n * b * es, V, vbytes))
     return fail(FE_EINVAL, "fe_block_update_gram: W overlaps V");
+  const size_t va = std::min<size_t>(16, 4 * es);  // the fused kernels' vector loads
+  if (fused && (reinterpret_cast<uintptr_t>(W) % va || reinterpret_cast<uintptr_t>(V) % va ||
+                ((size_t)stride * es) % va))
+    return fail(FE_EINVAL, "fe_block_update_gram: W and the blocks must be %zu-byte aligned", va);
   hipStream_t s = (hipStream_t)stream;
   const size_t np = gram_partials_doubles(n, nblk * b + b, b);
   double* part = nullptr;
   hipError_t e = hipMallocAsync((void**)&part, np * sizeof(double), s);
   if (e != hipSuccess)
     return fail(FE_ENOMEM, "fe_block_update_gram: hipMallocAsync: %s", hipGetErrorString(e));
-  fe_status st = update_gram_launch(W, n, b, V, nblk, stride, C, Cout, part, dt, s);
+  fe_status st = fused ? cgs_mid_launch(W, n, b, V, nblk, stride, C, Cout, part, dt, s)
+                       : update_gram_launch(W, n, b, V, nblk, stride, C, Cout, part, dt, s);
   hipError_t e2 = hipFreeAsync(part, s);
   if (st != FE_OK) return st;
   if (e2 != hipSuccess)

@@ -265,8 +265,8 @@ __global__ __launch_bounds__(kGramWG) void gram_wide_kernel(const T* __restrict_
 
 // CGS2's middle step at b = 4 in one pass over [V W]: W <- W - V C1 and the
 // Gram partials of [V W']^T W' (the layout of gram_wide_kernel<T, 1, NPG>).
-// V has kv columns; W is V's block kv/4, so the lanes whose column group is
-// W's load its old values.  Each lane forms, in FP64, the dot products of its
+// V has kv columns; the lanes whose column group is W's (group kv/4) load
+// W's old values.  Each lane forms, in FP64, the dot products of its
 // 16 V columns with C1 (staged in LDS, zero past kv); a butterfly over the
 // four lanes holding the row's other column groups completes them.  W' is
 // rounded to T once: that value is stored (by one lane per row) and is what
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kGramWG) void cgs_mid_kernel(const T* __restrict__ 
     const int c0 = pg * 16 + 4 * blk;
     aval[pg] = c0 < k;
     isw[pg] = c0 == kv;
-    aoff[pg] = aval[pg] ? (int64_t)(c0 / B) * stride + (c0 % B) : 0;
+    aoff[pg] = (aval[pg] && !isw[pg]) ? (int64_t)(c0 / B) * stride + (c0 % B) : 0;
   }
   double acc[NPG];
 #pragma unroll
@@ -310,8 +310,9 @@ __global__ __launch_bounds__(kGramWG) void cgs_mid_kernel(const T* __restrict__ 
     A v[NPG][4], w[4];
 #pragma unroll
     for (int pg = 0; pg < NPG; ++pg) {
+      const T* src = isw[pg] ? W + rb : V + aoff[pg] + rb;
 #pragma unroll
-      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(V + aoff[pg] + rb + c, v[pg] + c);
+      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(src + c, v[pg] + c);
       const bool ok = rv && aval[pg];
 #pragma unroll
       for (int c = 0; c < 4; ++c) v[pg][c] = ok ? v[pg][c] : (A)0;
@@ -388,6 +389,110 @@ __global__ __launch_bounds__(kGramWG) void cgs_mid_kernel(const T* __restrict__ 
     const int i = l >> 4, bl = (l >> 2) & 3, j = l & 3;
     const int p = pg * 16 + 4 * bl + i;
     if (p < k) out[(int64_t)p * B + j] = red[pg][l];
+  }
+}
+
+// CGS2's middle step at b = 16: W <- W - V C1 (V: kv = 16 G columns) and the
+// Gram partials of [V W']^T W', one pass over V from memory.  Per 16-row
+// group a wavefront forms V C1 on v_mfma_f64_16x16x4f64 in the restart
+// contraction's layout (lane (i, k) holds row i, columns 4k..4k+3 of each
+// group; output lane j + 16 (i mod 4), register i / 4 = row 4 reg + k,
+// column j), rounds W' once to T, stores it, and passes it through a 2 KB
+// LDS tile to the Gram's layout (lane (i, k) of step s = row 4k + s, column
+// i), in which the G + 1 tiles of [V W']^T W' accumulate as in gram16_kernel.
+// The Gram re-reads the wavefront's V rows, which the update has just brought
+// into the caches.
+template <typename T, int G>
+__global__ __launch_bounds__(kGramWG) void cgs_mid16_kernel(const T* __restrict__ V,
+                                                            int64_t stride, T* __restrict__ W,
+                                                            int64_t n,
+                                                            const double* __restrict__ C1,
+                                                            int64_t rows_per_wg,
+                                                            double* __restrict__ partials) {
+  using A = typename Acc<T>::type;
+  constexpr int VEC = 16 / sizeof(T) < 4 ? 16 / sizeof(T) : 4;
+  constexpr int B = 16;
+  constexpr int kv = 16 * G, k = kv + B;
+  __shared__ double Cs[kv * B];          // C1 (kv x 16)
+  __shared__ double Wt[kGramWG / 64][256];  // per wavefront: W' rows r0..r0+15
+  for (int i = threadIdx.x; i < kv * B; i += kGramWG) Cs[i] = C1[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 acc[G + 1];
+#pragma unroll
+  for (int t = 0; t <= G; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r_end = min(n, r_begin + rows_per_wg);
+  for (int64_t r0 = r_begin + wave * kGramRowsPerIter; r0 < r_end;
+       r0 += (kGramWG / 64) * kGramRowsPerIter) {
+    asm volatile("" ::: "memory");  // keep the C1 reads inside the loop (no hoisting)
+    // V C1 for rows r0..r0+15 (row r0 + li clamped; rows past r_end not stored)
+    const int64_t ra = min(r0 + li, r_end - 1);
+    f64x4 u = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      A v[4];
+      const T* vp = V + (int64_t)g * stride + ra * B + 4 * lk;
+#pragma unroll
+      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(vp + c, v + c);
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+        u = __builtin_amdgcn_mfma_f64_16x16x4f64((double)v[st], Cs[(16 * g + 4 * lk + st) * B + li],
+                                                 u, 0, 0, 0);
+    }
+    // W' = W - V C1 in the output layout: register reg = row r0 + 4 reg + lk, column li
+#pragma unroll
+    for (int reg = 0; reg < 4; ++reg) {
+      const int64_t row = r0 + 4 * reg + lk;
+      const bool rv = row < r_end;
+      const int64_t rc = rv ? row : r_end - 1;
+      const double d = load_f64(W + rc * B + li) - u[reg];
+      const T t = to_storage<T, double>(d);
+      double wr;
+      if constexpr (sizeof(T) == 2)
+        wr = (double)bf16_to_f32(t);
+      else
+        wr = (double)t;
+      if (rv) W[rc * B + li] = t;
+      Wt[wave][(4 * reg + lk) * 16 + li] = rv ? wr : 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // [V W']^T W' over the same rows in the Gram layout
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const double bw = Wt[wave][(4 * lk + st) * 16 + li];
+      const int64_t row = r0 + 4 * lk + st;
+      const bool rv = row < r_end;
+      const int64_t rc = rv ? row : r_end - 1;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const double x = load_f64(V + (int64_t)g * stride + rc * B + li);
+        acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(rv ? x : 0.0, bw, acc[g], 0, 0, 0);
+      }
+      acc[G] = __builtin_amdgcn_mfma_f64_16x16x4f64(bw, bw, acc[G], 0, 0, 0);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // the tile's reads finish before the next rows' writes
+  }
+  // wavefront partials added in wavefront order (deterministic)
+  __shared__ double red[G + 1][4][64];
+  for (int w = 0; w < kGramWG / 64; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int t = 0; t <= G; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[t][r][lane] = (w == 0 ? 0.0 : red[t][r][lane]) + acc[t][r];
+    }
+    __syncthreads();
+  }
+  double* out = partials + (int64_t)blockIdx.x * k * B;
+  for (int idx = threadIdx.x; idx < (G + 1) * 4 * 64; idx += kGramWG) {
+    const int l = idx & 63, r = (idx >> 6) & 3, t = idx >> 8;
+    const int p = 16 * t + 4 * r + (l >> 4), q = l & 15;
+    out[(int64_t)p * B + q] = red[t][r][l];
   }
 }
 
@@ -596,6 +701,36 @@ __global__ __launch_bounds__(256) void update_kernel(T* W, int64_t n,
 }
 
 // Any b: one thread per output element.
+// In-place right multiplication W <- beta W + alpha W C (nblk == 1, b <= 16)
+// at widths without a specialised kernel: one thread per row reads its whole
+// row before writing any of it (the per-element kernel below would let one
+// wavefront overwrite a row another is still reading).  Same arithmetic and
+// order as update_generic.
+template <typename T>
+__global__ __launch_bounds__(256) void update_inplace_generic(T* W, int64_t n, int32_t b,
+                                                              const double* __restrict__ C,
+                                                              double alpha, double beta) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double x[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) x[c] = c < b ? load_f64(W + r * b + c) : 0.0;
+  double y[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c < b && q < b) acc = fma(x[c], C[c * b + q], acc);
+    acc *= alpha;
+    if (beta != 0.0) acc = fma(beta, x[q], acc);
+    y[q] = acc;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    if (q < b) W[r * b + q] = to_storage<T, double>(y[q]);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void update_generic(T* __restrict__ W, int64_t n, int32_t b,
                                                       const T* __restrict__ V, int32_t nblk,
@@ -770,6 +905,9 @@ fe_status update_t(void* W, int64_t n, int32_t b, const void* V, int32_t nblk, i
     break;
   if (lds <= 64 * 1024 && (b == 1 || b == 2 || b == 4 || b == 8 || b == 16)) {
     switch (b) { FE_UPD(1) FE_UPD(2) FE_UPD(4) FE_UPD(8) FE_UPD(16) }
+  } else if (W == V && nblk == 1 && b <= 16) {
+    hipLaunchKernelGGL((update_inplace_generic<T>), dim3((uint32_t)g), dim3(256), 0, s, Wp, n, b,
+                       C, alpha, beta);
   } else {
     const int64_t ge = (n * b + 255) / 256;
     if (ge > 0x7FFFFFFF) return fail(FE_EUNSUPPORTED, "update: n*b too large");
@@ -1120,6 +1258,31 @@ fe_status gram_launch(const void* V, int32_t nblk, int64_t stride, const void* W
 }
 
 template <typename T>
+fe_status cgs_mid16_t(void* W, int64_t n, const void* V, int32_t nblk_v, int64_t stride,
+                      const double* C1, double* Cout, double* partials, hipStream_t s) {
+  const int32_t k = nblk_v * 16 + 16;
+  if (nblk_v < 1 || k > 128) return fail(FE_EUNSUPPORTED, "cgs_mid: %d columns at b = 16", k);
+  const int gx = gram_sets(n);
+  int64_t rows_per_wg = (n + gx - 1) / gx;
+  rows_per_wg = (rows_per_wg + 15) / 16 * 16;
+  const T* Vp = static_cast<const T*>(V);
+  T* Wp = static_cast<T*>(W);
+#define FE_MID16(G)                                                                            \
+  case G:                                                                                      \
+    hipLaunchKernelGGL((cgs_mid16_kernel<T, G>), dim3(gx), dim3(kGramWG), 0, s, Vp, stride, Wp, \
+                       n, C1, rows_per_wg, partials);                                          \
+    break;
+  switch (nblk_v) { FE_MID16(1) FE_MID16(2) FE_MID16(3) FE_MID16(4) FE_MID16(5) FE_MID16(6) FE_MID16(7) }
+#undef FE_MID16
+  FE_HIP(hipGetLastError());
+  const int len = k * 16;
+  hipLaunchKernelGGL(reduce_partials, dim3((len + 63) / 64), dim3(1024), 0, s, partials, gx, len,
+                     1.0, Cout);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+template <typename T>
 fe_status cgs_mid_t(void* W, int64_t n, const void* V, int32_t nblk_v, int64_t stride,
                     const double* C1, double* Cout, double* partials, hipStream_t s) {
   const int32_t kv = nblk_v * 4, k = kv + 4;
@@ -1152,13 +1315,29 @@ fe_status cgs_mid_t(void* W, int64_t n, const void* V, int32_t nblk_v, int64_t s
   return FE_OK;
 }
 
-fe_status cgs_mid_launch(void* W, int64_t n, const void* V, int32_t nblk_v, int64_t stride,
-                         const double* C1, double* Cout, double* partials, fe_dtype dt,
-                         hipStream_t s) {
-  switch (dt) {
-    case FE_F64: return cgs_mid_t<double>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
-    case FE_F32: return cgs_mid_t<float>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
-    case FE_BF16: return cgs_mid_t<bf16_t>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
+bool cgs_mid_supported(int32_t b, int32_t nblk_v) {
+  if (b == 4) return nblk_v >= 1 && nblk_v * 4 + 4 <= 128;
+  if (b == 16) return nblk_v >= 1 && nblk_v * 16 + 16 <= 128;
+  return false;
+}
+
+fe_status cgs_mid_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk_v,
+                         int64_t stride, const double* C1, double* Cout, double* partials,
+                         fe_dtype dt, hipStream_t s) {
+  if (!cgs_mid_supported(b, nblk_v))
+    return fail(FE_EUNSUPPORTED, "cgs_mid: b=%d with %d basis blocks", b, nblk_v);
+  if (b == 16) {
+    switch (dt) {
+      case FE_F64: return cgs_mid16_t<double>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
+      case FE_F32: return cgs_mid16_t<float>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
+      case FE_BF16: return cgs_mid16_t<bf16_t>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
+    }
+  } else {
+    switch (dt) {
+      case FE_F64: return cgs_mid_t<double>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
+      case FE_F32: return cgs_mid_t<float>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
+      case FE_BF16: return cgs_mid_t<bf16_t>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
+    }
   }
   return fail(FE_EINVAL, "cgs_mid: bad dtype");
 }

@@ -98,12 +98,14 @@ fe_status chol_second_launch(const double* G, int32_t b, const double* R1, doubl
 fe_status update_gram_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk,
                              int64_t blk_stride, const double* C, double* Cout, double* partials,
                              fe_dtype dt, hipStream_t s);
-// CGS2's middle step at b = 4 (solver-internal): W <- W - V[:, :4 nblk_v] C1,
-// then Cout ((4 nblk_v + 4) x 4) = [V W']^T W' with the rounded W'; W is V's
-// block nblk_v.  FE_EUNSUPPORTED beyond 128 columns.  partials as for gram_launch.
-fe_status cgs_mid_launch(void* W, int64_t n, const void* V, int32_t nblk_v, int64_t blk_stride,
-                         const double* C1, double* Cout, double* partials, fe_dtype dt,
-                         hipStream_t s);
+// CGS2's middle step in one pass over V, at b = 4 or 16: W <- W - V[:, :b nblk_v] C1,
+// then Cout ((b nblk_v + b) x b) = [V W']^T W' with the rounded W' (W its own
+// n x b block, not overlapping V).  Up to 128 columns of [V W]
+// (cgs_mid_supported); partials as for gram_launch.
+bool cgs_mid_supported(int32_t b, int32_t nblk_v);
+fe_status cgs_mid_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk_v,
+                         int64_t blk_stride, const double* C1, double* Cout, double* partials,
+                         fe_dtype dt, hipStream_t s);
 fe_status update_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk,
                         int64_t blk_stride, const double* C, double alpha, double beta,
                         fe_dtype dt, hipStream_t s);

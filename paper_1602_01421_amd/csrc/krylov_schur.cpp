@@ -374,10 +374,10 @@ class Solver {
     double* dC2 = dC + (size_t)(k + b) * b;
     double* flag = rec + (size_t)m * b + (size_t)b * b;
     FE_TRY(gram(nk + 1, W, dC1));
-    if (b == 4 && k + b <= 128) {
+    if (cgs_mid_supported(b, nk)) {
       // first update and second Gram in one pass over [V W]
       prof.begin(P_GRAM);
-      FE_TRY(cgs_mid_launch(W, n, V, nk, stride, dC1, dC2, dPart, dt, s));
+      FE_TRY(cgs_mid_launch(W, n, b, V, nk, stride, dC1, dC2, dPart, dt, s));
       prof.end();
       ++gram_calls;
       ++update_calls;

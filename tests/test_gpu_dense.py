@@ -101,6 +101,24 @@ def test_update_in_place_right_multiply(fe):
     assert np.allclose(host(Wd), W @ M, rtol=1e-14, atol=1e-13)
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("b", [3, 5, 12, 4, 16])
+def test_update_in_place_every_width(fe, dt, b):
+    """W <- 2 W - W C in place (W == V, one block) at widths whose rows
+    straddle wavefronts (b = 3, 5, 12) and at the specialised widths: every
+    row is read before any of it is written, so the result is exact on small
+    integers."""
+    n = 10_007
+    W = S.small_ints((n, b), seed=44, lo=-3, hi=3)
+    C = S.small_ints((b, b), seed=45, lo=-2, hi=2)
+    Wd = dev(W, DT[dt])
+    fe.fe_block_update(Wd, Wd, dev(C, torch.float64), alpha=-1.0, beta=2.0)
+    want = O.block_update(W, W, C, alpha=-1.0, beta=2.0)
+    if dt == "bf16":
+        want = O.round_bf16(want)
+    assert np.array_equal(host(Wd), want)
+
+
 def test_update_beta_zero_ignores_nan(fe):
     n, b = 100, 4
     W = torch.full((n, b), float("nan"), dtype=torch.float32, device="cuda")
@@ -156,6 +174,46 @@ def test_update_gram_normal(fe, dt, n, nblk, b):
     assert np.all(np.abs(Cout - O.gram(X, got)) <= bound)
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("b,nblk", [(4, 1), (4, 3), (4, 7), (4, 11), (4, 15), (4, 19), (4, 23),
+                                    (4, 27), (4, 31), (16, 1), (16, 2), (16, 3), (16, 4),
+                                    (16, 5), (16, 6), (16, 7)])
+@pytest.mark.parametrize("n", [1, 17, 40003])
+def test_fused_cgs_step_every_tile_count(fe, dt, b, nblk, n):
+    """The solver's one-pass CGS2 middle step (b = 4: column groups of 16 in
+    one workgroup slice; b = 16: G basis tiles on 16 x 16 MFMA), for every
+    tile count up to 128 columns of [V W] and for row counts below, at and
+    off the 16-row group: on small integers W' and [V W']^T W' are exact."""
+    V = S.small_ints((nblk, n, b), seed=31, lo=-3, hi=3)
+    W = S.small_ints((n, b), seed=32, lo=-3, hi=3)
+    C = S.small_ints((nblk * b, b), seed=33, lo=-3, hi=3)
+    Wd = dev(W, DT[dt])
+    Cout = host(fe.fe_block_update_gram(Wd, dev(V, DT[dt]), dev(C, torch.float64)))
+    Vf = V.transpose(1, 0, 2).reshape(n, nblk * b)
+    Wn = O.block_update(W, Vf, C, alpha=-1.0, beta=1.0)
+    if dt == "bf16":
+        Wn = O.round_bf16(Wn)
+    assert np.array_equal(host(Wd), Wn)
+    assert np.array_equal(Cout, O.gram(np.hstack([Vf, Wn]), Wn))
+
+
+@pytest.mark.parametrize("b,nblk", [(4, 27), (16, 6)])
+def test_fused_cgs_step_matches_separate_calls(fe, b, nblk):
+    """N(0,1) inputs, FP64: the fused step against fe_block_update followed by
+    fe_gram (the same arithmetic up to the order of the FP64 sums)."""
+    n = 300001
+    Vd = dev(S.normal((nblk, n, b), seed=34), torch.float64)
+    W0 = dev(S.normal((n, b), seed=35), torch.float64)
+    C = dev(S.normal((nblk * b, b), seed=36), torch.float64)
+    W1, W2 = W0.clone(), W0.clone()
+    Cf = host(fe.fe_block_update_gram(W1, Vd, C))
+    fe.fe_block_update(W2, Vd, C, alpha=-1.0, beta=1.0)
+    Cs = host(fe.fe_gram(torch.cat([Vd, W2.unsqueeze(0)]), W2))
+    mag = np.abs(host(W0)) + np.abs(host(Vd).transpose(1, 0, 2).reshape(n, -1)) @ np.abs(host(C))
+    assert np.all(np.abs(host(W1) - host(W2)) <= 1e-14 * mag)
+    assert np.allclose(Cf, Cs, rtol=1e-11, atol=1e-8)
+
+
 def test_update_gram_equals_separate_calls(fe):
     n, nblk, b = 20000, 6, 8
     Vd = dev(S.normal((nblk, n, b), seed=27), torch.float32)
@@ -180,8 +238,13 @@ def test_update_gram_rejects(fe):
     with pytest.raises(fe.FeError) as e:
         fe.fe_block_update_gram(W3, V3, torch.zeros((6, 3), dtype=torch.float64, device="cuda"))
     assert e.value.status == fe.FE_EUNSUPPORTED
-    V17 = torch.zeros((17, 100, 4), dtype=torch.float32, device="cuda")  # k = 68 > 64
+    V32 = torch.zeros((32, 100, 4), dtype=torch.float32, device="cuda")  # k + b = 132 > 128
     W4 = torch.zeros((100, 4), dtype=torch.float32, device="cuda")
     with pytest.raises(fe.FeError) as e:
-        fe.fe_block_update_gram(W4, V17, torch.zeros((68, 4), dtype=torch.float64, device="cuda"))
+        fe.fe_block_update_gram(W4, V32, torch.zeros((128, 4), dtype=torch.float64, device="cuda"))
+    assert e.value.status == fe.FE_EUNSUPPORTED
+    V9 = torch.zeros((9, 100, 8), dtype=torch.float32, device="cuda")  # b = 8: k = 72 > 64
+    W8 = torch.zeros((100, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(fe.FeError) as e:
+        fe.fe_block_update_gram(W8, V9, torch.zeros((72, 8), dtype=torch.float64, device="cuda"))
     assert e.value.status == fe.FE_EUNSUPPORTED
