@@ -60,10 +60,11 @@ def ptr(a: np.ndarray):
     return ctypes.c_void_p(a.ctypes.data)
 
 
-from .csr import csr_from_edges, csr_build, degrees  # noqa: E402
+from .csr import csr_from_edges, csr_build, csr_directed, degrees  # noqa: E402
 from .ops import (spmm, gram, block_update, col_norms, max_threads, round_bf16,  # noqa: E402
                   spmm_rows_from_edges)
 from .dense_eig import jacobi_eigh  # noqa: E402
 from .rng import philox4x32_10, refill_column  # noqa: E402
 from .krylov_schur import krylov_schur, KSResult, restart_keep, ritz_scale, EPS23  # noqa: E402
 from .certify import certify  # noqa: E402
+from .svd import svds  # noqa: E402

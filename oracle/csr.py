@@ -43,5 +43,21 @@ def csr_from_edges(n: int, src: np.ndarray, dst: np.ndarray):
     return row_ptr, cols
 
 
+def csr_directed(n: int, src: np.ndarray, dst: np.ndarray):
+    """Pattern CSR of a directed graph: row u lists the distinct v != u with
+    an arc (u, v), ascending (no symmetrising).  The transpose is
+    csr_directed(n, dst, src)."""
+    s = np.asarray(src, dtype=np.int64)
+    d = np.asarray(dst, dtype=np.int64)
+    keep = s != d
+    key = np.unique(s[keep] * np.int64(n) + d[keep])
+    rows = key // n
+    cols = (key - rows * n).astype(np.int32)
+    deg = np.bincount(rows, minlength=n).astype(np.int64)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(deg, out=row_ptr[1:])
+    return row_ptr, cols
+
+
 def degrees(row_ptr: np.ndarray) -> np.ndarray:
     return np.diff(row_ptr)

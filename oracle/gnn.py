@@ -58,13 +58,19 @@ def ahat(row_ptr, col_idx, dinv, H):
     return dinv[:, None] * spmm(row_ptr, col_idx, dinv[:, None] * H)
 
 
-def forward(row_ptr, col_idx, H0, params):
+def forward(row_ptr, col_idx, H0, params, transform_inputs=None):
+    """transform_inputs: None (exact), or a rounding function applied to the
+    operands of each layer's dense transform (S, H and the weights W, U) as
+    they enter it: the reading of the network's BF16 storage (BF16 operands,
+    wider accumulation; the bias, the output projection and the cached
+    activations stay unrounded)."""
+    rnd = transform_inputs if transform_inputs is not None else (lambda x: x)
     dinv = inv_sqrt_degree(row_ptr)
     H = H0
     cache = {"dinv": dinv, "H": [H0], "S": [], "Z": []}
     for l in range(LAYERS):
         S = ahat(row_ptr, col_idx, dinv, H)
-        Z = S @ params[f"W{l}"] + H @ params[f"U{l}"] + params[f"b{l}"]
+        Z = rnd(S) @ rnd(params[f"W{l}"]) + rnd(H) @ rnd(params[f"U{l}"]) + params[f"b{l}"]
         H = np.maximum(Z, 0.0)
         cache["S"].append(S)
         cache["Z"].append(Z)

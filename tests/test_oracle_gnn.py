@@ -128,3 +128,20 @@ def test_adam_global_norm_clipping():
     st2 = {}
     G.adam_step({"a": np.zeros(2), "b": np.zeros((1, 1))}, g, st2, lr=0.01, clip=10.0)
     assert np.allclose(st2["m_a"], 0.1 * g["a"], rtol=1e-15)  # norm below clip: unchanged
+
+
+def test_forward_rounding_hook():
+    """The rounding hook only touches the transforms' operands: identity
+    rounding reproduces the exact forward, and BF16 rounding moves the output
+    by about the BF16 unit roundoff, not more."""
+    n, s, d = S.chung_lu_edges(600, alpha=2.2, mean_deg=8, seed=5)
+    rp, ci = O.csr_from_edges(n, s, d)
+    params = G.init_params(3)
+    F = G.features(rp, S.normal((n, 15), seed=6))
+    X0, c0 = G.forward(rp, ci, F, params)
+    X1, c1 = G.forward(rp, ci, F, params, transform_inputs=lambda x: x)
+    assert np.array_equal(X0, X1)
+    Xb, cb = G.forward(rp, ci, F, params, transform_inputs=O.round_bf16)
+    err = np.linalg.norm(Xb - X0) / np.linalg.norm(X0)
+    assert 1e-5 < err < 3e-2
+    assert np.array_equal(cb["H"][0], c0["H"][0]) and np.array_equal(cb["S"][0], c0["S"][0])

@@ -198,3 +198,61 @@ def test_certificate_bounds_hold_on_known_spectra():
     assert np.all(err <= resid) and np.all(err <= kt) and np.all(kt < resid)
     theta0, resid0, _ = O.certify(rp, ci, V)   # exact eigenvectors
     assert np.allclose(theta0, lam, atol=1e-13) and resid0.max() < 1e-13
+
+
+# --------------------------------------------------- directed graphs, SVD
+def _dense_directed(n, rp, ci):
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, ci[rp[i]:rp[i + 1]]] = 1.0
+    return A
+
+
+def test_csr_directed_definition_and_transpose():
+    n, s, d = S.rmat_edges(9, seed=5)
+    rp, ci = O.csr_directed(n, s, d)
+    rpt, cit = O.csr_directed(n, d, s)
+    A = _dense_directed(n, rp, ci)
+    assert np.array_equal(A.T, _dense_directed(n, rpt, cit))
+    assert np.all(np.diag(A) == 0)
+    want = np.zeros((n, n))
+    keep = s != d
+    want[s[keep], d[keep]] = 1.0
+    assert np.array_equal(A, want)
+    assert not np.array_equal(A, A.T)  # R-MAT arcs are directed
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_svds_matches_dense_svd(seed):
+    """Directed R-MAT, n = 512: the oracle's A^T A Krylov-Schur against
+    numpy's dense SVD (LAPACK, an independent routine)."""
+    n, s, d = S.rmat_edges(9, seed=seed)
+    rp, ci = O.csr_directed(n, s, d)
+    rpt, cit = O.csr_directed(n, d, s)
+    sig, V, r = O.svds(rp, ci, rpt, cit, n, 6, 4, 32, 1e-12, S.normal((n, 4), seed=3))
+    assert r.converged
+    want = np.linalg.svd(_dense_directed(n, rp, ci), compute_uv=False)[:6]
+    assert np.allclose(sig, want, rtol=1e-10)
+    A = _dense_directed(n, rp, ci)
+    assert np.allclose(A.T @ (A @ V), V * sig ** 2, atol=1e-8 * sig[0] ** 2)
+
+
+def test_svds_closed_forms():
+    # out-star: one row with p ones -> sigma_1 = sqrt(p); complete bipartite
+    # arcs K_{p -> q} -> sigma_1 = sqrt(p q); the rest 0
+    p = 40
+    src = np.zeros(p, dtype=np.int32)
+    dst = np.arange(1, p + 1, dtype=np.int32)
+    n = p + 1
+    rp, ci = O.csr_directed(n, src, dst)
+    rpt, cit = O.csr_directed(n, dst, src)
+    sig, _, r = O.svds(rp, ci, rpt, cit, n, 1, 4, 16, 1e-12, S.normal((n, 4), seed=1))
+    assert abs(sig[0] - np.sqrt(p)) < 1e-12
+    P, Q = 7, 9
+    src = np.repeat(np.arange(P), Q).astype(np.int32)
+    dst = (P + np.tile(np.arange(Q), P)).astype(np.int32)
+    n = P + Q
+    rp, ci = O.csr_directed(n, src, dst)
+    rpt, cit = O.csr_directed(n, dst, src)
+    sig, _, r = O.svds(rp, ci, rpt, cit, n, 1, 2, 8, 1e-12, S.normal((n, 2), seed=2))
+    assert abs(sig[0] - np.sqrt(P * Q)) < 1e-12
