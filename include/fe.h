@@ -200,7 +200,8 @@ typedef struct {
                             column ratio below max(eta, 1e-6) are factored column by
                             column instead of by Cholesky QR twice. */
   int32_t profile;       /* 1 = time each kernel class with HIP events */
-  int32_t verbose;       /* 1 = print one line per restart to stderr */
+  int32_t verbose;       /* 1 = print one line per restart to stderr; 2 = also the
+                            block QR's column decisions on its careful path */
   int32_t mixed;         /* 1 = mixed-precision storage: the subspace starts in BF16;
                             once the worst wanted residual estimate drops below
                             mixed_switch, or gains less than 10% on the best of the
@@ -227,6 +228,9 @@ typedef struct {
                             a few KB of pinned host memory).  Its contents on entry do
                             not matter; on return they are undefined. */
   uint64_t workspace_bytes; /* size of `workspace` */
+  int32_t keep;          /* Ritz vectors kept at a restart: 0 -> m - block * max(1,
+                            (m - nev) / (2 block)); otherwise nev <= keep <= m - block
+                            with m - keep a multiple of block (FE_EINVAL if not) */
 } fe_ks_opts;
 
 /* Per-solve report (all times in seconds). */
@@ -260,12 +264,16 @@ typedef struct {
  * generic eigen-iteration with the block extension).  block = b vectors per
  * step, m = subspace size (m % block == 0, 1 <= nev <= m - block, nev <= 64,
  * m <= 256, block in {1,2,4,8,16}, m + block <= n; the restart keeps
- * p = m - block * max(1, (m - nev) / (2 block)) vectors, p <= 128), tol > 0: pair i is converged when its
+ * p = opts->keep or m - block * max(1, (m - nev) / (2 block)) vectors,
+ * p <= 128), tol > 0: pair i is converged when its
  * Krylov-Schur residual estimate is <= tol * max(eps^(2/3), |theta_i|), eps
  * the FP64 unit roundoff.
  * Final check (FP64 whatever the storage dtype): the Ritz vectors X = V Y are
  * formed in FP64, multiplied by A in FP64, and each value returned is the
- * Rayleigh quotient x^T A x / x^T x with its explicit residual.
+ * Rayleigh quotient x^T A x / x^T x with its explicit residual.  The stop
+ * test trusts the Krylov relation, which a basis stored in FP32 or BF16
+ * carries only to that storage's unit roundoff u_s, so there the explicit
+ * residual may exceed tol |theta_i| by about 2 u_s |lambda_1|.
  * Outputs: evals (host double[nev], pairs ordered by Ritz value |theta|
  * descending, ties to the larger theta); evecs (device n x nev in opts->dt,
  * original vertex order, 2-norm 1 up to storage rounding) or NULL; rep (host)
@@ -282,6 +290,27 @@ typedef struct {
 fe_status fe_krylov_schur(const fe_csr *A, int32_t nev, int32_t block, int32_t m, double tol,
                           const fe_ks_opts *opts, double *evals, void *evecs,
                           fe_ks_report *rep);
+
+/*
+ * The nsv largest singular values of a square pattern matrix A that need not
+ * be symmetric (a directed graph: the paper's billion-node run is the SVD of
+ * its directed page graph), with the same block Krylov-Schur applied to the
+ * symmetric positive semidefinite operator A^T A: each step's product is
+ * A^T (A X), two sparse products.  A and At are handles of the matrix and of
+ * its transpose (fe_csr_build on the same arcs with src and dst swapped,
+ * both without FE_SYMMETRIZE and without FE_RELABEL_BY_DEGREE).  Options,
+ * shapes, tol (relative to each eigenvalue of A^T A) and the report as in
+ * fe_krylov_schur (rep->resid: residuals of A^T A x = lambda x; the width-
+ * block products are counted once per A^T A application).
+ * Outputs: svals (host double[nsv], descending) = sqrt of the eigenvalues of
+ * A^T A; vecs (device n x nsv in opts->dt) the right singular vectors, or
+ * NULL; left singular vectors are A v / sigma (fe_spmm with A).
+ * Errors: as fe_krylov_schur; FE_EINVAL when A and At differ in size or are
+ * relabelled; FE_EUNSUPPORTED with opts->workspace.
+ */
+fe_status fe_svds(const fe_csr *A, const fe_csr *At, int32_t nsv, int32_t block, int32_t m,
+                  double tol, const fe_ks_opts *opts, double *svals, void *vecs,
+                  fe_ks_report *rep);
 
 /*
  * Device memory fe_krylov_schur needs for these arguments (the options that

@@ -171,10 +171,14 @@ def _ritz_order(theta: np.ndarray) -> np.ndarray:
 
 def krylov_schur(spmm, n: int, nev: int, b: int, m: int, tol: float, X0: np.ndarray,
                  max_restarts: int = 500, seed: int = 0, eta: float = 1e-10,
-                 eta_chol: float = 1e-6) -> KSResult:
-    """spmm(X) must return A @ X for an (n, cols) float64 array."""
+                 eta_chol: float = 1e-6, keep: int = 0) -> KSResult:
+    """spmm(X) must return A @ X for an (n, cols) float64 array.  keep: Ritz
+    vectors kept at a restart (0: restart_keep(m, b, nev)); a multiple of b
+    away from m, at least nev."""
     if m % b or nev > m - b or nev < 1 or tol <= 0 or m + b > n:
         raise ValueError("need m % b == 0, 1 <= nev <= m - b, tol > 0, m + b <= n")
+    if keep and (keep < nev or keep > m - b or (m - keep) % b):
+        raise ValueError("need nev <= keep <= m - b and (m - keep) % b == 0")
     V = np.zeros((n, m), order="F")
     T = np.zeros((m, m))
     Bk = np.zeros((b, m))
@@ -212,7 +216,7 @@ def krylov_schur(spmm, n: int, nev: int, b: int, m: int, tol: float, X0: np.ndar
         history.append((restarts, spmm_calls, float(np.max(rho[:nev] / scale[:nev]))))
         if conv.all() or restarts >= max_restarts:
             break
-        p = restart_keep(m, b, nev)
+        p = keep if keep else restart_keep(m, b, nev)
         V[:, :p] = V @ Y[:, :p]
         T = np.zeros((m, m))
         T[np.arange(p), np.arange(p)] = theta[:p]

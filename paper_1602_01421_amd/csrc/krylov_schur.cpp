@@ -45,6 +45,12 @@ static double ritz_scale(double theta) {
   return std::max(std::fabs(theta), std::cbrt(2.220446049250313e-16 * 2.220446049250313e-16));
 }
 
+// Ritz vectors kept at a restart: the caller's count, or the default
+// m - b max(1, floor((m - nev) / (2 b))) (a reading; m - p stays a multiple of b).
+static int restart_size(int m, int b, int nev, int keep) {
+  return keep > 0 ? keep : m - b * std::max(1, (m - nev) / (2 * b));
+}
+
 static double secs(clk::time_point a, clk::time_point b) {
   return std::chrono::duration<double>(b - a).count();
 }
@@ -180,6 +186,9 @@ static void inv_upper(int na, const double* R, int ld, double* Ri, int ldi) {
 class Solver {
  public:
   const Csr& A;
+  const Csr* At = nullptr;  // set for the singular value problem: the operator is A^T A
+  void* Tb = nullptr;       // n x b block between the two products (A^T A)
+  double* T64 = nullptr;    // n x nev FP64, the final check's A X (A^T A)
   int nev, b, m;
   double tol, eta, eta_chol;
   fe_ks_opts o;
@@ -301,6 +310,7 @@ class Solver {
     FE_TRY(dev.get((void**)&dRec, sizeof(double) * rec_stride * (m / b + 1)));
     FE_TRY(host.get(&hRec, rec_stride * (m / b + 1)));
     FE_TRY(dev.get((void**)&dR1, sizeof(double) * b * b));
+    if (At) FE_TRY(dev.get(&Tb, (size_t)n * b * std::max(es, dtype_size(dt_final))));
     T.assign((size_t)m * m, 0.0);
     Bk.assign((size_t)b * m, 0.0);
     return FE_OK;
@@ -334,14 +344,18 @@ class Solver {
   }
   fe_status spmm(const void* X, void* Y, int cols) {
     prof.begin(P_SPMM);
-    fe_status st = spmm_launch(A, X, Y, cols, dt, s);
+    fe_status st = At ? spmm_launch(A, X, Tb, cols, dt, s) : spmm_launch(A, X, Y, cols, dt, s);
+    if (st == FE_OK && At) st = spmm_launch(*At, Tb, Y, cols, dt, s);
     prof.end();
     spmm_cols += cols;
-    bytes[P_SPMM] += 4.0 * A.nnz + 8.0 * (n + 1) + 2.0 * n * cols * es;
+    bytes[P_SPMM] += (At ? 2.0 : 1.0) * (4.0 * A.nnz + 8.0 * (n + 1) + 2.0 * n * cols * es);
     return st;
   }
+  // hM is pinned host memory reused by the next factor: the copy must have
+  // read it before the host writes it again, so the upload waits for it.
   fe_status upload_M() {
     FE_HIP(hipMemcpyAsync(dM, hM, sizeof(double) * b * b, hipMemcpyHostToDevice, s));
+    FE_HIP(hipStreamSynchronize(s));
     return FE_OK;
   }
   // W <- W * hM (in place)
@@ -521,6 +535,17 @@ class Solver {
     for (int j = 0; j < b; ++j) nb[j] = std::sqrt(std::max(0.0, hC1[(size_t)(k + j) * b + j]));
     C.assign((size_t)k * b, 0.0);
     for (int i = 0; i < k * b; ++i) C[i] = hC1[i] + (nk > 0 ? hC2[i] : 0.0);
+    if (o.verbose >= 2) {
+      int bad1 = 0, bad2 = 0;
+      for (int i = 0; i < (k + b) * b; ++i) {
+        bad1 += !std::isfinite(hC1[i]);
+        if (nk > 0) bad2 += !std::isfinite(hC2[i]);
+      }
+      fprintf(stderr, "[fe_krylov_schur] careful step %d (block %d): non-finite Gram entries %d / %d;"
+              " norms before projection:", step, wb, bad1, bad2);
+      for (int j = 0; j < b; ++j) fprintf(stderr, " %.3e", hC1[(size_t)(k + j) * b + j]);
+      fprintf(stderr, "\n");
+    }
     // A non-finite column (a caller's start block) is dependent outright and
     // is overwritten by its refill draws at once: the right multiplications
     // below combine all columns, and NaN x 0 would spread it.
@@ -542,6 +567,10 @@ class Solver {
       double nw = 0.0;
       FE_TRY(project_column(wb, j, acc, R, &nw));
       min_ratio = std::min(min_ratio, nb[j] > 0.0 ? nw / nb[j] : 0.0);
+      if (o.verbose >= 2)
+        fprintf(stderr, "[fe_krylov_schur]   column %d: norm after %.3e (G_jj %.3e), ratio %.3e -> %s\n",
+                j, nw, hG[j * b + j], nb[j] > 0.0 ? nw / nb[j] : 0.0,
+                (!(nw > eta * nb[j]) || !(nw > 0.0)) ? "dependent" : "kept");
       if (!(nw > eta * nb[j]) || !(nw > 0.0)) {
         dep.push_back(j);
         continue;
@@ -584,6 +613,8 @@ class Solver {
       std::vector<double> Rdrop((size_t)b * b, 0.0);  // a refill's coefficients are not kept
       double nw = 0.0;
       FE_TRY(project_column(wb, j, acc, Rdrop, &nw));
+      if (o.verbose >= 2)
+        fprintf(stderr, "[fe_krylov_schur]   refill %d: norm %.3e (G_jj %.3e)\n", j, nw, hG[j * b + j]);
       if (!(nw > 0.0) || !std::isfinite(nw))
         return fail(FE_EBREAKDOWN, "fe_krylov_schur: refill of column %d is dependent (step %d)", j, step);
       FE_TRY(scale_column(wb, j, 1.0 / nw));
@@ -672,6 +703,9 @@ class Solver {
           const Pending& P = pend[i];
           const double* rec = hRec + (size_t)P.wb * rec_stride;
           if (rec[(size_t)m * b + (size_t)b * b] != 0.0) {
+            if (o.verbose >= 2)
+              fprintf(stderr, "[fe_krylov_schur] step %d flagged (%g): redone on the careful path\n",
+                      P.step0 + 1, rec[(size_t)m * b + (size_t)b * b]);
             const int dropped = (int)(pend.size() - i);
             spmm_calls -= dropped;
             spmm_cols -= dropped * b;
@@ -770,7 +804,7 @@ class Solver {
         }
       }
       // restart
-      const int p = m - b * std::max(1, (m - nev) / (2 * b));
+      const int p = restart_size(m, b, nev, o.keep);
       for (int i = 0; i < m; ++i)
         for (int j = 0; j < p; ++j) hY[(size_t)i * p + j] = Y[(size_t)i * m + j];
       FE_HIP(hipMemcpyAsync(dY, hY, sizeof(double) * m * p, hipMemcpyHostToDevice, s));
@@ -806,7 +840,13 @@ class Solver {
     FE_TRY(combine_launch(X, nev, n, b, V, m / b, stride, dY, dYpad, dt, s));
     prof.end();
     prof.begin(P_OTHER);
-    FE_TRY(spmm_launch(A, X, AX, nev, FE_F64, s));
+    if (At) {
+      FE_TRY(dev.get((void**)&T64, (size_t)n * nev * sizeof(double)));
+      FE_TRY(spmm_launch(A, X, T64, nev, FE_F64, s));
+      FE_TRY(spmm_launch(*At, T64, AX, nev, FE_F64, s));
+    } else {
+      FE_TRY(spmm_launch(A, X, AX, nev, FE_F64, s));
+    }
     prof.end();
     spmm_cols += nev;
     prof.begin(P_OTHER);
@@ -873,7 +913,10 @@ fe_status ks_check(const fe::Csr* A, int32_t nev, int32_t block, int32_t m, doub
   if (block < 1 || block > 16 || m < 1 || m % block || nev < 1 || nev > m - block || !(tol > 0))
     return fail(FE_EINVAL, "fe_krylov_schur: need 1<=block<=16, m %% block == 0, 1<=nev<=m-block, tol>0");
   if (o.which != 0) return fail(FE_EUNSUPPORTED, "fe_krylov_schur: only largest magnitude");
-  const int p = m - block * std::max(1, (m - nev) / (2 * block));
+  if (o.keep && (o.keep < nev || o.keep > m - block || (m - o.keep) % block))
+    return fail(FE_EINVAL, "fe_krylov_schur: keep=%d needs nev <= keep <= m - block, (m - keep) %% block == 0",
+                o.keep);
+  const int p = restart_size(m, block, nev, o.keep);
   if (m > 256 || p > 128 || nev > 64)
     return fail(FE_EUNSUPPORTED, "fe_krylov_schur: m=%d keeps p=%d (limits m<=256, p<=128, nev<=64)", m, p);
   if (block != 1 && block != 2 && block != 4 && block != 8 && block != 16)
@@ -884,6 +927,30 @@ fe_status ks_check(const fe::Csr* A, int32_t nev, int32_t block, int32_t m, doub
   return FE_OK;
 }
 }  // namespace
+
+extern "C" fe_status fe_svds(const fe_csr* A, const fe_csr* At, int32_t nsv, int32_t block,
+                             int32_t m, double tol, const fe_ks_opts* opts, double* svals,
+                             void* vecs, fe_ks_report* rep) {
+  using namespace fe;
+  if (!A || !At || !svals) return fail(FE_EINVAL, "fe_svds: NULL argument");
+  if (A->n != At->n || A->nnz != At->nnz)
+    return fail(FE_EINVAL, "fe_svds: A (n=%lld, nnz=%lld) and At (n=%lld, nnz=%lld) differ",
+                (long long)A->n, (long long)A->nnz, (long long)At->n, (long long)At->nnz);
+  if (A->relabeled || At->relabeled)
+    return fail(FE_EINVAL, "fe_svds: handles must keep the vertex numbering (no FE_RELABEL_BY_DEGREE)");
+  fe_ks_opts o;
+  std::memset(&o, 0, sizeof o);
+  if (opts) o = *opts;
+  if (o.workspace) return fail(FE_EUNSUPPORTED, "fe_svds: no caller workspace");
+  FE_TRY(ks_check(A, nsv, block, m, tol, o));
+  clear_error();
+  std::vector<double> lam((size_t)nsv);
+  Solver S(*A, nsv, block, m, tol, o);
+  S.At = At;
+  const fe_status st = S.run(lam.data(), vecs, rep);
+  for (int i = 0; i < nsv; ++i) svals[i] = std::sqrt(std::max(lam[(size_t)i], 0.0));
+  return st;
+}
 
 extern "C" fe_status fe_ks_workspace_bytes(const fe_csr* A, int32_t nev, int32_t block, int32_t m,
                                            const fe_ks_opts* opts, uint64_t* bytes) {

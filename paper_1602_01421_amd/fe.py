@@ -24,6 +24,7 @@ FE_GRAPH_DEFAULT = FE_SYMMETRIZE | FE_DEDUPE | FE_DROP_SELF
 EXPORTED = ("fe_last_error", "fe_version", "fe_csr_build", "fe_csr_from_csr", "fe_csr_info",
             "fe_csr_perm", "fe_csr_export", "fe_csr_free", "fe_spmm", "fe_gram", "fe_gram_noalloc",
             "fe_block_update", "fe_block_update_gram", "fe_krylov_schur", "fe_ks_workspace_bytes",
+            "fe_svds",
             "fe_dense_symeig", "fe_gnn_param_count",
             "fe_gnn_create", "fe_gnn_free", "fe_gnn_get_params", "fe_gnn_set_params",
             "fe_gnn_forward", "fe_gnn_backward", "fe_gnn_adam")
@@ -43,7 +44,7 @@ class KsOpts(ctypes.Structure):
                 ("verbose", ctypes.c_int32), ("mixed", ctypes.c_int32),
                 ("mixed_switch", ctypes.c_double), ("start_check", ctypes.c_int32),
                 ("start_drop", ctypes.c_double), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_uint64)]
+                ("workspace_bytes", ctypes.c_uint64), ("keep", ctypes.c_int32)]
 
 
 class KsReport(ctypes.Structure):
@@ -92,6 +93,8 @@ def lib():
             "fe_dense_symeig": [i32, P, P, P],
             "fe_ks_workspace_bytes": [P, i32, i32, i32, ctypes.POINTER(KsOpts),
                                       ctypes.POINTER(ctypes.c_uint64)],
+            "fe_svds": [P, P, i32, i32, i32, f64, ctypes.POINTER(KsOpts), P, P,
+                        ctypes.POINTER(KsReport)],
             "fe_gnn_create": [ctypes.c_uint64, i32, ctypes.POINTER(P)],
             "fe_gnn_get_params": [P, P],
             "fe_gnn_set_params": [P, P],
@@ -337,7 +340,7 @@ def fe_krylov_schur(A: Csr, nev: int, block: int, m: int, tol: float, dtype=None
                     want_vectors: bool = True, profile: bool = False,
                     verbose: bool = False, mixed: bool = False,
                     mixed_switch: float = 0.0, start_check: int = 0,
-                    start_drop: float = 0.0, workspace=None) -> KsResult:
+                    start_drop: float = 0.0, workspace=None, keep: int = 0) -> KsResult:
     """Block Krylov-Schur for the nev largest-magnitude eigenpairs (see fe.h).
     workspace: optional device tensor of at least fe_ks_workspace_bytes bytes."""
     import torch
@@ -356,6 +359,7 @@ def fe_krylov_schur(A: Csr, nev: int, block: int, m: int, tol: float, dtype=None
     o.mixed_switch = mixed_switch
     o.start_check = start_check
     o.start_drop = start_drop
+    o.keep = keep
     o.hip_stream = _stream(stream).value
     if start is not None:
         if start.shape != (A.n, block) or start.dtype != dtype:
@@ -380,6 +384,44 @@ def fe_krylov_schur(A: Csr, nev: int, block: int, m: int, tol: float, dtype=None
                     t_update=rep.t_update, t_other_dev=rep.t_other_dev,
                     bytes_spmm=rep.bytes_spmm, bytes_gram=rep.bytes_gram,
                     bytes_update=rep.bytes_update, t_host=rep.t_host,
+                    t_total=rep.t_total, start_fallback=rep.start_fallback,
+                    device_allocs=rep.device_allocs)
+
+
+def fe_svds(A: Csr, At: Csr, nsv: int, block: int, m: int, tol: float, dtype=None, start=None,
+            seed: int = 0, max_restarts: int = 0, stream=None, want_vectors: bool = True,
+            profile: bool = False) -> KsResult:
+    """Largest singular values of a pattern matrix from handles of A and A^T
+    (see fe.h).  Returns a KsResult whose evals are the singular values
+    (descending) and whose evecs are the right singular vectors."""
+    import torch
+    if dtype is None:
+        dtype = torch.float64
+    o = KsOpts()
+    o.dt = {torch.float64: FE_F64, torch.float32: FE_F32, torch.bfloat16: FE_BF16}[dtype]
+    o.seed = seed
+    o.max_restarts = max_restarts
+    o.profile = int(profile)
+    o.hip_stream = _stream(stream).value
+    if start is not None:
+        if start.shape != (A.n, block) or start.dtype != dtype:
+            raise FeError(FE_EINVAL, "start must be (n, block) in the solve dtype")
+        o.start = _dev_ptr(start).value
+    sv = np.zeros(nsv, dtype=np.float64)
+    vecs = torch.empty((A.n, nsv), dtype=dtype, device="cuda") if want_vectors else None
+    rep = KsReport()
+    st = lib().fe_svds(A.handle, At.handle, nsv, block, m, tol, ctypes.byref(o), _np_ptr(sv),
+                       _dev_ptr(vecs) if vecs is not None else None, ctypes.byref(rep))
+    _check(st, allow=(FE_ENOCONV,))
+    return KsResult(evals=sv, evecs=vecs, status=st, restarts=rep.restarts,
+                    spmm_calls=rep.spmm_calls, spmm_cols=rep.spmm_cols,
+                    converged=rep.converged, refills=rep.refills, gram_calls=rep.gram_calls,
+                    update_calls=rep.update_calls, switch_restart=rep.switch_restart,
+                    spmm_calls_low=rep.spmm_calls_low, rho=np.array(rep.rho[:nsv]),
+                    ritz=np.array(rep.ritz[:nsv]), resid=np.array(rep.resid[:nsv]),
+                    t_spmm=rep.t_spmm, t_gram=rep.t_gram, t_update=rep.t_update,
+                    t_other_dev=rep.t_other_dev, bytes_spmm=rep.bytes_spmm,
+                    bytes_gram=rep.bytes_gram, bytes_update=rep.bytes_update, t_host=rep.t_host,
                     t_total=rep.t_total, start_fallback=rep.start_fallback,
                     device_allocs=rep.device_allocs)
 
