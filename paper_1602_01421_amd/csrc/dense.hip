@@ -460,20 +460,30 @@ __global__ __launch_bounds__(kGramWG) void cgs_mid16_kernel(const T* __restrict_
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // [V W']^T W' over the same rows in the Gram layout
+    // [V W']^T W' over the same rows in the Gram layout (lane (i, k) of step s:
+    // row 4k + s, column i), V as 16-byte column groups and a quad transpose
+    double bw[4];
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const double bw = Wt[wave][(4 * lk + st) * 16 + li];
-      const int64_t row = r0 + 4 * lk + st;
-      const bool rv = row < r_end;
-      const int64_t rc = rv ? row : r_end - 1;
+    for (int st = 0; st < 4; ++st) bw[st] = Wt[wave][(4 * lk + st) * 16 + li];
+    const int qx = li & 3, jq = li >> 2;
+    const int64_t grow = r0 + 4 * lk + qx;  // the row this lane loads
+    const bool gv = grow < r_end;
+    const int64_t gb = (gv ? grow : r_end - 1) * B + 4 * jq;
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const double x = load_f64(V + (int64_t)g * stride + rc * B + li);
-        acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(rv ? x : 0.0, bw, acc[g], 0, 0, 0);
-      }
-      acc[G] = __builtin_amdgcn_mfma_f64_16x16x4f64(bw, bw, acc[G], 0, 0, 0);
+    for (int g = 0; g < G; ++g) {
+      A v[4];
+#pragma unroll
+      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(V + (int64_t)g * stride + gb + c, v + c);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = gv ? v[c] : (A)0;
+      quad_transpose(v, qx);
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+        acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)v[st], bw[st], acc[g], 0, 0, 0);
     }
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+      acc[G] = __builtin_amdgcn_mfma_f64_16x16x4f64(bw[st], bw[st], acc[G], 0, 0, 0);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();  // the tile's reads finish before the next rows' writes
   }
@@ -519,9 +529,10 @@ __global__ __launch_bounds__(1024) void reduce_partials(const double* __restrict
 // Same contraction for b = 16 on v_mfma_f64_16x16x4f64 (A lane i + 16k,
 // B lane j + 16k, D lane j + 16 (i mod 4), register i / 4): the output tile is
 // 16 V columns x 16 W columns and the contraction runs over rows, four per
-// step.  Lane (i, k) of step s reads column i of row r0 + 4k + s, so the 16
-// lanes of each quarter-wave read 16 consecutive columns of one row: no
-// transposes and no idle MFMA lanes.  (At b = 8 half of each tile would be
+// step.  Lane (i, k) of step s needs column i of row r0 + 4k + s; it is
+// loaded as one 16-byte group of four columns per lane (lane x of quad q
+// loads columns 4q..4q+3 of row r0 + 4k + x) and a quad transpose hands the
+// operands over, four times fewer load instructions than element loads.  (At b = 8 half of each tile would be
 // padding; the quad-transpose kernel is faster there.)  NPG 16-column V tiles
 // per workgroup slice;
 // tiles past k are fed zeros (their MFMAs are not skipped, which keeps every
@@ -532,19 +543,21 @@ __global__ __launch_bounds__(kGramWG) void gram16_kernel(const T* __restrict__ V
                                                          int32_t b, int32_t k,
                                                          int64_t rows_per_wg,
                                                          double* __restrict__ partials) {
+  using A = typename Acc<T>::type;
+  constexpr int VEC = 16 / sizeof(T) < 4 ? 16 / sizeof(T) : 4;
+  constexpr int B = 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  const int x = li & 3, jq = li >> 2;  // quad lane, quad: columns 4 jq .. 4 jq + 3
   const int p_base = blockIdx.y * (16 * kGramPG);
   int64_t aoff[NPG];
   bool aval[NPG];
 #pragma unroll
   for (int pg = 0; pg < NPG; ++pg) {
-    const int c = p_base + 16 * pg + li;
-    aval[pg] = c < k;
-    aoff[pg] = aval[pg] ? (int64_t)(c / b) * stride + (c % b) : 0;
+    const int c0 = p_base + 16 * pg;  // a whole block of 16 columns
+    aval[pg] = c0 < k;
+    aoff[pg] = aval[pg] ? (int64_t)(c0 / B) * stride + 4 * jq : 0;
   }
-  const bool bval = li < b;
-  const int lq = bval ? li : 0;
   f64x4 acc[NPG];
 #pragma unroll
   for (int pg = 0; pg < NPG; ++pg) acc[pg] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -552,20 +565,34 @@ __global__ __launch_bounds__(kGramWG) void gram16_kernel(const T* __restrict__ V
   const int64_t r_end = min(n, r_begin + rows_per_wg);
   for (int64_t r0 = r_begin + wave * kGramRowsPerIter; r0 < r_end;
        r0 += (kGramWG / 64) * kGramRowsPerIter) {
-    // unconditional loads from clamped addresses, masked afterwards
+    // each lane loads 4 consecutive columns of row r0 + 4 lk + x (clamped,
+    // masked afterwards); the quad transpose then gives lane (4 jq + x) column
+    // 4 jq + x of rows r0 + 4 lk + u, u = 0..3: the MFMA operands of steps u
+    const int64_t row = r0 + 4 * lk + x;
+    const bool rv = row < r_end;
+    const int64_t rb = (rv ? row : r_end - 1) * B;
     double bw[4], a[4][NPG];
+    {
+      A w[4];
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const int64_t row = r0 + 4 * lk + st;
-      const bool rv = row < r_end;
-      const int64_t rb = (rv ? row : r_end - 1) * b;
-      const double w = load_f64(W + rb + lq);
-      bw[st] = (rv && bval) ? w : 0.0;
+      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(W + rb + 4 * jq + c, w + c);
 #pragma unroll
-      for (int pg = 0; pg < NPG; ++pg) {
-        const double x = load_f64(V + aoff[pg] + rb);
-        a[st][pg] = (rv && aval[pg]) ? x : 0.0;
-      }
+      for (int c = 0; c < 4; ++c) w[c] = rv ? w[c] : (A)0;
+      quad_transpose(w, x);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) bw[u] = (double)w[u];
+    }
+#pragma unroll
+    for (int pg = 0; pg < NPG; ++pg) {
+      A v[4];
+#pragma unroll
+      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(V + aoff[pg] + rb + c, v + c);
+      const bool ok = rv && aval[pg];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = ok ? v[c] : (A)0;
+      quad_transpose(v, x);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u][pg] = (double)v[u];
     }
 #pragma unroll
     for (int st = 0; st < 4; ++st)
