@@ -621,8 +621,18 @@ struct Ws {
     g->arena_cap = g->arena_need;
     return FE_OK;
   }
+  // Overflow allocations go back to the stream-ordered pool, and the pool is
+  // trimmed here: otherwise the pool would hand the memory back to the device
+  // at some later synchronisation of the caller's, inside unrelated work.
   ~Ws() {
     for (void* p : ptrs) (void)hipFreeAsync(p, s);
+    if (!ptrs.empty()) {
+      int dev = 0;
+      hipMemPool_t pool = nullptr;
+      if (hipStreamSynchronize(s) == hipSuccess && hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess)
+        (void)hipMemPoolTrimTo(pool, 0);
+    }
     g->arena_need = std::max(g->arena_need, need);
   }
   template <class T>

@@ -1,12 +1,15 @@
 """Learned-start network on the GPU against the FP64 oracle.
 
-Bars: BF16 forward (FP32 accumulation): output X within 2e-2 relative
-(Frobenius, per column), loss within 1e-2, each parameter tensor's gradient
-pointing the same way (cosine >= 0.99; the subspace-loss gradient is a near
-cancellation that amplifies BF16 rounding of the activations).  FP32 compute
-mode: X within 1e-4, loss within 1e-5, each gradient tensor within 1e-3
-relative (Frobenius).  An Adam step matches the oracle's Adam on the GPU's
-own gradients to 1e-5.
+Bars: BF16 forward (BF16 transform operands, FP32 accumulation) against the
+exact oracle: output X within 2e-2 relative (Frobenius, per column).  Against
+the oracle whose transform operands are rounded to BF16 the same way (the
+BF16 reading of the network): X within 1e-3, loss within 1e-4, every
+parameter tensor's gradient within 1e-2 relative (Frobenius) -- what is left
+is FP32 accumulation and the rare operand whose FP32 and FP64 values round
+to different BF16 neighbours, amplified by the subspace loss's near
+cancellation.  FP32 compute mode: X within 1e-4, loss within 1e-5, each
+gradient tensor within 1e-4 relative.  An Adam step matches the oracle's
+Adam on the GPU's own gradients to 1e-5.
 """
 import numpy as np
 import pytest
@@ -67,19 +70,24 @@ def test_gradients_match_oracle(fe, relabel, compute, n):
     X = net.forward(A, zt).double().cpu().numpy()
     loss, g = net.backward(A, zt, torch.tensor(V, dtype=torch.float32, device="cuda"),
                            want_grads=True)
-    Xo, cache = G.forward(rp, ci, G.features(rp, z), params)
+    rounding = O.round_bf16 if compute == "bf16" else None
+    Xo, cache = G.forward(rp, ci, G.features(rp, z), params, transform_inputs=rounding)
     lo = G.loss(Xo, V)
     go = G.backward(rp, ci, params, cache, G.loss_grad(Xo, V))
     gd = fe.gnn_unflatten(g)
+    errs = {name: rel(gd[name], go[name]) for name in go}
+    print(f"{compute}: X {rel(X, Xo):.2e} loss {abs(loss - lo):.2e} grads max "
+          f"{max(errs.values()):.2e} ({max(errs, key=errs.get)})")
     if compute == "f32":
         assert rel(X, Xo) < 1e-4
         assert abs(loss - lo) < 1e-5
         for name in go:
-            assert rel(gd[name], go[name]) < 1e-3, (name, rel(gd[name], go[name]))
+            assert errs[name] < 1e-4, (name, errs[name])
     else:
-        assert abs(loss - lo) < 1e-2
+        assert rel(X, Xo) < 1e-3
+        assert abs(loss - lo) < 1e-4
         for name in go:
-            assert cosine(gd[name], go[name]) > 0.99, (name, cosine(gd[name], go[name]))
+            assert errs[name] < 1e-2, (name, errs[name])
 
 
 def test_adam_step_matches_oracle(fe):
