@@ -1,17 +1,22 @@
 """Benchmark: block Krylov-Schur hot path on one MI355X.
 
-Workload: R-MAT scale 22 (4,194,304 vertices, edge factor 16,
-a/b/c/d = .57/.19/.19/.05, seed 22), symmetrised, deduplicated, self-loops
-dropped, 0/1 pattern CSR relabelled by degree.  One step = one full block
-Krylov-Schur solve for the 8 largest-magnitude eigenpairs, block 4,
-subspace 48, FP32 storage, tol 1e-6, random start (every row of the hot
+Workload (default): R-MAT scale 27 (134,217,728 vertices, edge factor 16,
+a/b/c/d = .57/.19/.19/.05, seed 27), symmetrised, deduplicated, self-loops
+dropped: a 0/1 pattern CSR of 4.2e9 stored nonzeros with 64-bit offsets,
+relabelled by degree -- one GPU's share at real shape.  One step = one full
+block Krylov-Schur solve for the 8 largest-magnitude eigenpairs, FP32
+storage, tol 1e-6, random start, block 16, subspace 112 (every row of the hot
 path: sparse products, CGS2 Gram/updates, block QR, Rayleigh-Ritz, restarts
-and the FP64 final check).
+and the FP64 final check).  The configured block 8 / subspace 48 does not
+converge on this graph in 500 restarts (three eigenvalues within 2e-4 of
+each other); block 16 / 112 is the fastest converging shape measured.
 
 value = sparse work of the solve (nnz x columns multiplied) / solve time,
-in GEdge*col/s.  The JSON line also carries the SpMM-only sweep over block
-widths 1, 2, 4, 8, 16 (FP32), the roofline of the dominant kernel and the
-CPU oracle timed on a bounded sample of the same workload.
+in GEdge*col/s.  The JSON line also carries the product alone at the solve's
+width and the sweep over widths 1..16 (FP32) at scale 27 and at scale 22,
+the roofline of the dominant kernel, the time to 8 eigenpairs from the
+learned start block against random starts, and the CPU oracle timed on a
+bounded sample of the same workload, on all host cores and on one.
 """
 from __future__ import annotations
 
@@ -28,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "SpMM GEdge·col/s & % HBM roofline; time-to-8-eigs learned vs random start"
 
 
-PROFILE = os.path.join(ROOT, "profiles", "bench_rmat22_f32.md")
+PROFILE = os.path.join(ROOT, "profiles", "spmm_rmat27_b16_f32.md")
 
 
 def measured_traffic(kernel: str):
@@ -54,7 +59,8 @@ def counter_calibration_copy():
     FETCH_SIZE/WRITE_SIZE profile of this script can scale the counters; then
     five more copies timed with HIP events: the measured streaming bandwidth
     (bytes read + written per second, median), the practical ceiling beside
-    the 8 TB/s datasheet peak."""
+    the 8 TB/s datasheet peak; then a 1 GiB permutation gather for the same
+    scaling on random line-sized reads."""
     import numpy as np
     import torch
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -72,6 +78,16 @@ def counter_calibration_copy():
         e1.synchronize()
         times.append(e0.elapsed_time(e1) * 1e-3)
     del src, flush, dst
+    # a permutation gather of known bytes: 2^23 rows of 128 bytes (one cache
+    # line each) read once in random order, so FETCH_SIZE can be scaled for
+    # gathers as well as for streams
+    rows = torch.ones((1 << 23, 32), dtype=torch.float32, device="cuda")
+    perm = torch.randperm(1 << 23, device="cuda")
+    flush = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
+    flush.add_(1.0)
+    gathered = rows.index_select(0, perm)
+    torch.cuda.synchronize()
+    del rows, perm, flush, gathered
     return 2.0 * (1 << 30) / float(np.median(times)) / 1e9
 
 
@@ -103,44 +119,97 @@ def time_spmm(P, A, b, dtype, stream, reps):
     return [e0.elapsed_time(e1) * 1e-3 for e0, e1 in ev]
 
 
-def cpu_baseline(n, s, d, nnz, restarts=2):
-    """The oracle as it stands on this host: the beginning of the same solve
-    (the first expansion, m/b = 12 sparse products of width 4 with CGS2 and
-    block QR, then `restarts` thick restarts of 5 products each, and the final
-    width-8 check) on the same graph, all host cores, FP64; about 10-15 s."""
+def host_info():
+    import platform
+    import subprocess
+    info = {"nproc": os.cpu_count(), "machine": platform.machine()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "CPU(s)", "Thread(s) per core", "Socket(s)",
+                             "CPU max MHz", "NUMA node(s)"):
+                info[k.strip()] = v.strip()
+    except Exception:
+        pass
+    try:
+        info["sched_affinity"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    return info
+
+
+def cpu_baseline(n, s, d, block, m, budget_s=12.0):
+    """The oracle as it stands, on this host's cores and on one core: one
+    expansion step of the same solve restricted to a bounded sample of rows
+    (a contiguous range of original vertex ids, which the generator's random
+    relabel makes a uniform sample): the FP64 product of those rows with a
+    full n x block X, then CGS2 of the sample rows against an m-column basis
+    (two Grams, two updates).  Rows are added until the step takes about
+    `budget_s` seconds.  The oracle's CSR build is not timed."""
     import numpy as np
     import fe_synth as S
     import oracle as O
+    from oracle.krylov_schur import _cgs2
+    threads = max(1, min(len(os.sched_getaffinity(0)), O.max_threads()))
     t0 = time.time()
-    rp, ci = O.csr_from_edges(n, s, d)
+    rp, ci = O.csr_build(n, s, d, threads=threads)
     t_csr = time.time() - t0
-    threads = O.max_threads()
-    X0 = S.normal((n, 4), seed=3)
-    t0 = time.time()
-    r = O.krylov_schur(lambda X: O.spmm(rp, ci, X, threads=threads), n, 8, 4, 48, 1e-6, X0,
-                       max_restarts=restarts)
-    t = time.time() - t0
-    cols = 4 * r.spmm_calls + 8
-    return {"value": nnz * cols / t / 1e9, "unit": "GEdge·col/s", "cores": threads,
+    X = S.normal((n, block), seed=3)
+
+    def step(rows, th):
+        sub = rp[: rows + 1]
+        Vs = S.normal((rows, m), seed=4)
+        t = time.perf_counter()
+        W = _rows_spmm(O, sub, ci, X, th)
+        _cgs2(Vs, W)
+        return time.perf_counter() - t, int(sub[-1])
+
+    out = {}
+    for label, th in (("all", threads), ("one", 1)):
+        rows = 1 << 14
+        t, e = step(rows, th)
+        while t < budget_s / 4 and rows < n:
+            rows = min(n, int(rows * max(2.0, budget_s / max(t, 1e-3) / 2)))
+            t, e = step(rows, th)
+        out[label] = {"threads": th, "rows": rows, "nnz": e, "s": t,
+                      "gedge_col_s": e * block / t / 1e9}
+    del X
+    a, o = out["all"], out["one"]
+    return {"value": a["gedge_col_s"], "unit": "GEdge·col/s", "cores": a["threads"],
             "kind": "oracle",
-            "sample": f"beginning of the same solve: {r.spmm_calls} width-4 products with "
-                      f"CGS2/CholQR2 ({r.restarts} restarts) plus the width-8 final check, "
-                      f"FP64; {t:.1f} s (oracle CSR build {t_csr:.1f} s not timed)"}
+            "one_core": {"value": o["gedge_col_s"], "rows": o["rows"], "s": o["s"]},
+            "host": host_info(),
+            "sample": f"one expansion step of the same solve on rows [0, {a['rows']}) of "
+                      f"{n} ({a['nnz']} nonzeros): FP64 product with an n x {block} block, "
+                      f"then CGS2 against {m} basis columns; {a['s']:.1f} s on {a['threads']} "
+                      f"threads (one core: {o['rows']} rows, {o['s']:.1f} s); oracle CSR build "
+                      f"{t_csr:.0f} s not timed"}
+
+
+def _rows_spmm(O, sub_rp, ci, X, threads):
+    """Rows [0, len(sub_rp) - 1) of A X with the oracle's product loop."""
+    import numpy as np
+    rows = sub_rp.shape[0] - 1
+    Y = np.empty((rows, X.shape[1]))
+    O.lib().oracle_spmm(rows, O.ptr(np.ascontiguousarray(sub_rp)), O.ptr(ci),
+                        O.ptr(X), X.shape[1], O.ptr(Y), threads)
+    return Y
 
 
 def learned_vs_random(P, A, stream, weights, tol, block, m, seeds=3):
     """Time to 8 eigenpairs from the learned start block vs random starts.
 
-    The same solve as the timed steps (FP32 storage, nev 8, `block`, `m`); for
-    block < 8 the network's 8 outputs are folded to `block` columns.  The
+    FP32 storage, nev 8 and tol as the timed steps, at its own shape (`block`
+    <= 8, the network's width; for block < 8 its 8 outputs are folded to
+    `block` columns).  The
     learned time is end to end: drawing the network's N(0,1) inputs on the
     GPU, inference, the fallback check and the solve.
     """
     import numpy as np
     import torch
     from paper_1602_01421_amd.learned import START_CHECK, START_DROP, learned_start
-    net = P.Gnn(seed=0, compute="bf16")
-    net.set_params(np.load(weights))
+    params = np.load(weights)
 
     def solve(start=None, seed=1):
         return P.fe_krylov_schur(A, 8, block, m, tol, dtype=torch.float32, start=start,
@@ -160,18 +229,23 @@ def learned_vs_random(P, A, stream, weights, tol, block, m, seeds=3):
     for k in range(seeds):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        # the network's inference workspace (about 1 KB per vertex) is released
+        # before the solve allocates its subspace
+        net = P.Gnn(seed=0, compute="bf16")
+        net.set_params(params)
         g = torch.Generator(device="cuda")
         g.manual_seed(1 + k)
         z = torch.randn((A.n, 15), generator=g, device="cuda", dtype=torch.float32)
         X = learned_start(net, A, z, torch.float32, block=block)
+        net.close()
+        del z
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - t0
         r = solve(start=X, seed=1 + k)
         torch.cuda.synchronize()
         learned.append((time.perf_counter() - t0, r.spmm_calls, r.status, t_inf, X is None,
                         r.start_fallback >= 0))
-        del z, X
-    net.close()
+        del X
     med = lambda xs: float(np.median(xs))  # noqa: E731
     res = {"block": block, "m": m, "tol": tol, "dtype": "f32", "seeds": seeds,
            "random_s": med([x[0] for x in rand]), "random_spmm": med([x[1] for x in rand]),
@@ -189,22 +263,44 @@ def learned_vs_random(P, A, stream, weights, tol, block, m, seeds=3):
     return res
 
 
+def sweep_spmm(P, A, stream, widths, reps, stream_gbs, tag):
+    import numpy as np
+    import torch
+    out = []
+    for b in widths:
+        ts = time_spmm(P, A, b, torch.float32, stream, reps)
+        t = float(np.median(ts))
+        by = spmm_bytes(A.n, A.nnz, b, 4)
+        out.append({"b": b, "us": t * 1e6, "us_p10": float(np.percentile(ts, 10)) * 1e6,
+                    "us_p90": float(np.percentile(ts, 90)) * 1e6, "reps": len(ts),
+                    "gedge_col_s": A.nnz * b / t / 1e9, "gbs": by / t / 1e9,
+                    "frac": by / t / 1e9 / HBM_PEAK_GBS,
+                    "frac_of_stream": by / t / 1e9 / stream_gbs})
+        log(f"{tag} spmm b={b:2d}: {t*1e6:9.1f} us  {A.nnz*b/t/1e9:8.1f} GEdge*col/s  "
+            f"{by/t/1e9:7.1f} GB/s ({100*by/t/1e9/HBM_PEAK_GBS:.1f}% of HBM)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--scale", type=int, default=22)
-    ap.add_argument("--block", type=int, default=4)
-    ap.add_argument("--m", type=int, default=48)
+    ap.add_argument("--scale", type=int, default=27)
+    ap.add_argument("--block", type=int, default=16)
+    ap.add_argument("--m", type=int, default=112)
     ap.add_argument("--mixed", action="store_true",
                     help="BF16 storage widened to FP32 when BF16 stalls (mixed-precision solve)")
     ap.add_argument("--sweep", default="1,2,4,8,16", help="SpMM-only widths (FP32)")
+    ap.add_argument("--sweep-scale", type=int, default=22,
+                    help="second graph for the SpMM-only sweep (0 to skip)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1602_01421_amd", "weights",
                                                       "gnn_start.npy"),
                     help="learned start-block weights ('' to skip the comparison)")
+    ap.add_argument("--learned-shape", default="8x120",
+                    help="block x m of the learned-vs-random comparison (block <= 8)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--spmm-reps", type=int, default=50)
+    ap.add_argument("--spmm-reps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path would "
@@ -221,31 +317,31 @@ def main():
     P.lib()
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    stream_gbs = counter_calibration_copy()
+    log(f"streaming copy: {stream_gbs:.0f} GB/s (read + write)")
+    widths = [int(x) for x in args.sweep.split(",") if x]
+
+    sweep2 = None
+    if args.sweep_scale and args.sweep_scale != args.scale:
+        n2, s2, d2 = S.rmat_edges(args.sweep_scale, seed=args.sweep_scale)
+        A2 = P.fe_csr_build(n2, s2, d2, P.FE_GRAPH_DEFAULT | P.FE_RELABEL_BY_DEGREE)
+        del s2, d2
+        sweep2 = {"scale": args.sweep_scale, "n": A2.n, "nnz": A2.nnz,
+                  "sweep": sweep_spmm(P, A2, stream, widths, 50, stream_gbs,
+                                      f"scale {args.sweep_scale}")}
+        A2.close()
+
     t0 = time.time()
     n, s, d = S.rmat_edges(args.scale, edge_factor=16, a=0.57, b=0.19, c=0.19, seed=args.scale)
     t_gen = time.time() - t0
+    log(f"R-MAT scale {args.scale}: {len(s)} samples ({t_gen:.1f} s)")
     t0 = time.time()
     A = P.fe_csr_build(n, s, d, P.FE_GRAPH_DEFAULT | P.FE_RELABEL_BY_DEGREE)
     t_build = time.time() - t0
     log(f"R-MAT scale {args.scale}: n={n} nnz={A.nnz} max_deg={A.max_deg} "
-        f"(generate {t_gen:.1f} s, fe_csr_build {t_build:.1f} s)")
+        f"(fe_csr_build {t_build:.1f} s)")
 
-    stream_gbs = counter_calibration_copy()
-    log(f"streaming copy: {stream_gbs:.0f} GB/s (read + write)")
-
-    # SpMM-only sweep (FP32)
-    sweep = []
-    for b in [int(x) for x in args.sweep.split(",") if x]:
-        ts = time_spmm(P, A, b, torch.float32, stream, args.spmm_reps)
-        t = float(np.median(ts))
-        by = spmm_bytes(A.n, A.nnz, b, 4)
-        sweep.append({"b": b, "us": t * 1e6, "us_p10": float(np.percentile(ts, 10)) * 1e6,
-                      "us_p90": float(np.percentile(ts, 90)) * 1e6, "reps": len(ts),
-                      "gedge_col_s": A.nnz * b / t / 1e9, "gbs": by / t / 1e9,
-                      "frac": by / t / 1e9 / HBM_PEAK_GBS,
-                      "frac_of_stream": by / t / 1e9 / stream_gbs})
-        log(f"spmm b={b:2d}: {t*1e6:8.1f} us  {A.nnz*b/t/1e9:8.1f} GEdge*col/s  "
-            f"{by/t/1e9:7.1f} GB/s ({100*by/t/1e9/HBM_PEAK_GBS:.1f}% of HBM)")
+    sweep = sweep_spmm(P, A, stream, widths, args.spmm_reps, stream_gbs, f"scale {args.scale}")
 
     # whole-path steps: one solve each
     nev, block, m, tol = 8, args.block, args.m, 1e-6
@@ -272,11 +368,13 @@ def main():
         results.append(r)
         log(f"step {k}: {times[-1]:.3f} s  status {r.status} restarts {r.restarts} "
             f"products {r.spmm_calls} max resid {r.resid.max():.2e} lambda1 {r.evals[0]:.8g}")
+        del r.evecs
     t_all = time.perf_counter() - t_all0
     value = A.nnz * cols / t_all / 1e9
 
     # per-kernel profile of one more solve (HIP events on the solve's stream)
     rp = solve(1, profile=True)
+    del rp.evecs
     classes = {"spmm": (rp.t_spmm, rp.bytes_spmm, rp.spmm_calls),
                "gram": (rp.t_gram, rp.bytes_gram, rp.gram_calls),
                "update": (rp.t_update, rp.bytes_update, rp.update_calls)}
@@ -286,13 +384,14 @@ def main():
     log("profile: " + ", ".join(f"{c} {v[0]*1e3:.1f} ms / {v[2]} launches "
                                  f"({v[1]/max(v[0],1e-12)/1e9:.0f} GB/s)" for c, v in classes.items())
         + f", other {rp.t_other_dev*1e3:.1f} ms, host {rp.t_host*1e3:.1f} ms, total {rp.t_total*1e3:.1f} ms")
-    default_cfg = args.scale == 22 and block == 4 and m == 48 and not args.mixed
+    default_cfg = args.scale == 27 and block == 16 and m == 112 and not args.mixed
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(dom) if default_cfg else None,
             "launches": calls_dom, "avg_launch_us": t_dom / calls_dom * 1e6,
             "algorithmic_bytes_per_launch": b_dom / calls_dom,
             "stream_copy_gbs": stream_gbs, "frac_of_stream": achieved / stream_gbs}
+    spmm_alone = next((x for x in sweep if x["b"] == block), None)
 
     out = {
         "metric": METRIC, "value": value, "unit": "GEdge·col/s", "n_gpus": 1,
@@ -307,21 +406,27 @@ def main():
                    "tol": tol, "relabel": "degree", "storage": "bf16->f32" if args.mixed else "f32"},
         "roofline": roof,
         "time_to_8_eigs_s": float(np.median(times)),
+        "spmm_alone_at_block": spmm_alone,
         "solve": {"restarts": [r.restarts for r in results],
                   "spmm_calls_bf16": [r.spmm_calls_low for r in results],
                   "spmm_calls": [r.spmm_calls for r in results],
                   "max_resid": [float(r.resid.max()) for r in results],
                   "evals": [float(x) for x in results[-1].evals]},
         "spmm_sweep": sweep,
-        "build_s": t_build,
+        "spmm_sweep_second_graph": sweep2,
+        "generate_s": t_gen, "build_s": t_build,
     }
     if args.weights and os.path.exists(args.weights):
-        out["learned_vs_random"] = learned_vs_random(P, A, stream, args.weights, tol, block, m)
+        lb, lm = (int(x) for x in args.learned_shape.split("x"))
+        out["learned_vs_random"] = learned_vs_random(P, A, stream, args.weights, tol, lb, lm)
+    A.close()
+    torch.cuda.empty_cache()
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(n, s, d, A.nnz)
-        log(f"cpu baseline: {out['cpu_baseline']['value']:.3f} GEdge*col/s on "
-            f"{out['cpu_baseline']['cores']} threads")
+        out["cpu_baseline"] = cpu_baseline(n, s, d, block, m)
+        cb = out["cpu_baseline"]
+        log(f"cpu baseline: {cb['value']:.3f} GEdge*col/s on {cb['cores']} threads, "
+            f"{cb['one_core']['value']:.3f} on one core")
     print(json.dumps(out), flush=True)
 
 

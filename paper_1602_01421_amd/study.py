@@ -25,11 +25,30 @@ gnn
     FP32 transforms), the training step (forward, loss, backward) and the
     Adam step, each timed with HIP events over repeated calls.
 
+svd
+    Directed R-MAT (default scale 27: the arcs of the same sample stream, not
+    symmetrised; deduplicated, self-loops dropped; the paper's directed page
+    graph is not available): the nsv largest singular values through
+    Krylov-Schur on A^T A (fe_svds, handles of A and A^T), for each shape in
+    --configs (BLOCKxM; the paper's SVD run used 2 vectors per block and a
+    basis of 2 x block x nsv), an FP64-storage reference (tol 1e-10) and FP32
+    storage (tol 1e-6); plus each product alone at the block width.
+
+ops
+    The dense subspace operations alone (the paper's dense-operation figure:
+    n = 60M rows, block 4, subspace m = 4 .. 512): fe_gram (V^T W, the
+    MvTransMv operation) and fe_block_update (W <- W + V C, MvTimesMatAddMv)
+    per m in FP32 (and FP64 up to --f64-max-m), with the algorithmic bytes
+    (n (m + b) s and n (m + 2 b) s), GB/s, the fraction of 8 TB/s and, for
+    the Gram, FP64 MFMA TFLOP/s.
+
 Each prints one JSON line; progress goes to stdout as the steps finish.
 
     python -m paper_1602_01421_amd.study precision --scale 24
     python -m paper_1602_01421_amd.study large --scale 27 --weights W.npy
     python -m paper_1602_01421_amd.study gnn
+    python -m paper_1602_01421_amd.study svd --scale 27
+    python -m paper_1602_01421_amd.study ops
 """
 from __future__ import annotations
 
@@ -268,6 +287,97 @@ def gnn(args):
     print(json.dumps(out), flush=True)
 
 
+def svd(args):
+    from . import fe as F
+    import torch
+    import fe_synth as S
+    t0 = time.perf_counter()
+    n, s, d = S.rmat_edges(args.scale, seed=args.scale)
+    t_gen = time.perf_counter() - t0
+    _log(f"[study] generated R-MAT scale {args.scale}: {len(s)} arcs in {t_gen:.1f} s")
+    directed = F.FE_DEDUPE | F.FE_DROP_SELF
+    t0 = time.perf_counter()
+    A = F.fe_csr_build(n, s, d, directed)
+    At = F.fe_csr_build(n, d, s, directed)
+    t_build = time.perf_counter() - t0
+    del s, d
+    gc.collect()
+    _log(f"[study] A: n={A.n} nnz={A.nnz} max out-degree {A.max_deg}; A^T max in-degree "
+         f"{At.max_deg} (both built in {t_build:.1f} s)")
+    out = {"study": "svd", "scale": args.scale, "n": A.n, "nnz": A.nnz,
+           "max_out_degree": A.max_deg, "max_in_degree": At.max_deg, "gen_s": t_gen,
+           "build_s": t_build, "nsv": args.nsv, "configs": []}
+    for cfg in args.configs.split(","):
+        b, m = (int(x) for x in cfg.split("x"))
+        rows = {"block": b, "m": m, "spmm_A": time_spmm(F, A, b, torch.float32),
+                "spmm_At": time_spmm(F, At, b, torch.float32), "solves": []}
+        ref = None
+        for dt, tol in ((torch.float64, 1e-10), (torch.float32, 1e-6)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = F.fe_svds(A, At, args.nsv, b, m, tol, dtype=dt, seed=1, want_vectors=False,
+                          max_restarts=args.max_restarts)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            row = {"storage": str(dt).replace("torch.", ""), "tol": tol, "status": int(r.status),
+                   "seconds": t, "applications": r.spmm_calls, "restarts": r.restarts,
+                   "max_resid": float(np.max(r.resid)), "svals": [float(x) for x in r.evals]}
+            if ref is None:
+                ref = r.evals
+            else:
+                row["max_sval_rel_err_vs_f64"] = float(np.max(np.abs(r.evals - ref) / ref))
+            rows["solves"].append(row)
+            _log(f"[study] svd {b}x{m} {row['storage']}: status {r.status} {t:.2f} s, "
+                 f"{r.spmm_calls} A^T A applications, max resid {row['max_resid']:.2e}, "
+                 f"sigma_1 {r.evals[0]:.8g}")
+        out["configs"].append(rows)
+    print(json.dumps(out), flush=True)
+
+
+def ops(args):
+    from . import fe as F
+    import torch
+    n, b = args.n, 4
+    out = {"study": "ops", "n": n, "b": b, "rows": []}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    for dt in (torch.float32, torch.float64):
+        es = torch.tensor([], dtype=dt).element_size()
+        for m in [int(x) for x in args.ms.split(",")]:
+            if dt == torch.float64 and m > args.f64_max_m:
+                continue
+            nblk = m // b
+            V = torch.randn((nblk, n, b), generator=g, device="cuda", dtype=torch.float32).to(dt)
+            W = torch.randn((n, b), generator=g, device="cuda", dtype=torch.float32).to(dt)
+            C = torch.randn((m, b), generator=g, device="cuda", dtype=torch.float64) * 1e-3
+            G = torch.empty((m, b), dtype=torch.float64, device="cuda")
+            res = {"dtype": str(dt).replace("torch.", ""), "m": m}
+            for name, fn, byts, flops in (
+                    ("gram", lambda: F.fe_gram(V, W, C=G), n * (m + b) * es, 2.0 * n * m * b),
+                    ("update", lambda: F.fe_block_update(W, V, C), n * (m + 2 * b) * es,
+                     2.0 * n * m * b)):
+                for _ in range(3):
+                    fn()
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                      for _ in range(args.reps)]
+                for e0, e1 in ev:
+                    e0.record()
+                    fn()
+                    e1.record()
+                torch.cuda.synchronize()
+                t = float(np.median([e0.elapsed_time(e1) / 1e3 for e0, e1 in ev]))
+                res[name] = {"ms": t * 1e3, "gbs": byts / t / 1e9,
+                             "frac": byts / t / 1e9 / HBM_PEAK_GBS, "tflops": flops / t / 1e12}
+            out["rows"].append(res)
+            _log(f"[study] ops {res['dtype']} m={m:3d}: gram {res['gram']['ms']:8.2f} ms "
+                 f"{res['gram']['gbs']:7.0f} GB/s ({100 * res['gram']['frac']:.0f}%), update "
+                 f"{res['update']['ms']:8.2f} ms {res['update']['gbs']:7.0f} GB/s "
+                 f"({100 * res['update']['frac']:.0f}%)")
+            del V, W, C, G
+            torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -292,7 +402,19 @@ def main():
     r.add_argument("--log2n", type=int, default=18)
     r.add_argument("--mean-deg", type=float, default=32.0)
     r.add_argument("--reps", type=int, default=20)
-    for sp in (p, q, r):
+    v = sub.add_parser("svd")
+    v.add_argument("--scale", type=int, default=27)
+    v.add_argument("--nsv", type=int, default=8)
+    v.add_argument("--configs", default="2x32,8x64",
+                   help="comma list of BLOCKxM shapes (2x32: the paper's 2 vectors per block, "
+                        "basis 2 x 2 x nsv)")
+    v.add_argument("--max-restarts", type=int, default=500)
+    o = sub.add_parser("ops")
+    o.add_argument("--n", type=int, default=60_000_000)
+    o.add_argument("--ms", default="4,8,16,32,64,128,256,512")
+    o.add_argument("--f64-max-m", type=int, default=256)
+    o.add_argument("--reps", type=int, default=5)
+    for sp in (p, q, r, v, o):
         sp.add_argument("--verbose", action="store_true",
                         help="one line per restart from the solver (stderr)")
     args = ap.parse_args()
@@ -300,7 +422,7 @@ def main():
     VERBOSE = args.verbose
     import torch
     torch.cuda.set_device(0)
-    {"precision": precision, "large": large, "gnn": gnn}[args.cmd](args)
+    {"precision": precision, "large": large, "gnn": gnn, "svd": svd, "ops": ops}[args.cmd](args)
 
 
 if __name__ == "__main__":
