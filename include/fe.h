@@ -157,6 +157,10 @@ fe_status fe_gram_noalloc(const void *V, int32_t nblk, int64_t blk_stride, const
  * (row-interval parallelism).  W may equal V only when nblk == 1 and b <= 16
  * (in-place right multiplication, W <- beta W + alpha W C); any other overlap
  * is FE_EINVAL.  With beta == 0, W is not read (NaNs in it do not propagate).
+ * At b = 8 and 16 with k <= 256 and V and the block stride aligned to
+ * min(16, 4 x element size) bytes, the solver's MFMA kernel runs (FP64 MFMA
+ * contraction, so the FP64 sums are taken in another order than the
+ * one-thread-per-row kernel used otherwise).
  * Errors: FE_EINVAL, FE_EDEVICE.
  */
 fe_status fe_block_update(void *W, int64_t n, int32_t b, const void *V, int32_t nblk,

@@ -408,6 +408,13 @@ fe_status fe_block_update(void* W, int64_t n, int32_t b, const void* V, int32_t 
     if (!(nblk == 1 && W == V && b <= 16))
       return fail(FE_EINVAL, "fe_block_update: W overlaps V (only W == V with nblk == 1, b <= 16 is allowed)");
   }
+  // at b = 8 and 16 the solver's MFMA kernel (V read as min(16, 4 x element
+  // size)-byte column groups, C staged in LDS for k <= 256)
+  const size_t va = std::min<size_t>(16, 4 * es);
+  if ((b == 8 || b == 16) && (int64_t)nblk * b <= 256 && reinterpret_cast<uintptr_t>(V) % va == 0 &&
+      ((size_t)stride * es) % va == 0)
+    return mult_update_launch(W, n, b, V, nblk, stride, C, alpha, beta, nullptr, dt,
+                              (hipStream_t)stream);
   return update_launch(W, n, b, V, nblk, stride, C, alpha, beta, dt, (hipStream_t)stream);
 }
 

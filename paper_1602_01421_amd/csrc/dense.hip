@@ -400,8 +400,21 @@ __global__ __launch_bounds__(kGramWG) void cgs_mid_kernel(const T* __restrict__ 
 // column j), rounds W' once to T, stores it, and passes it through a 2 KB
 // LDS tile to the Gram's layout (lane (i, k) of step s = row 4k + s, column
 // i), in which the G + 1 tiles of [V W']^T W' accumulate as in gram16_kernel.
-// The Gram re-reads the wavefront's V rows, which the update has just brought
-// into the caches.
+// V reaches the Gram layout from the registers the update used: a lane
+// permutation (ds_bpermute, no LDS storage) gives lane qx + 4 jq + 16 lk the
+// four columns 4 jq..4 jq+3 of row 4 lk + qx, then a quad transpose.  The
+// next group's V and W loads are issued before this group's W' and Gram
+// work, so one group's memory latency overlaps the previous group's MFMAs.
+__device__ __forceinline__ float lane_pull(float v, int src4) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_pull(double v, int src4) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(src4, (int)(u & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(src4, (int)(u >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <typename T, int G>
 __global__ __launch_bounds__(kGramWG) void cgs_mid16_kernel(const T* __restrict__ V,
                                                             int64_t stride, T* __restrict__ W,
@@ -413,73 +426,90 @@ __global__ __launch_bounds__(kGramWG) void cgs_mid16_kernel(const T* __restrict_
   constexpr int VEC = 16 / sizeof(T) < 4 ? 16 / sizeof(T) : 4;
   constexpr int B = 16;
   constexpr int kv = 16 * G, k = kv + B;
+  constexpr int64_t kStep = (kGramWG / 64) * kGramRowsPerIter;
   __shared__ double Cs[kv * B];          // C1 (kv x 16)
   __shared__ double Wt[kGramWG / 64][256];  // per wavefront: W' rows r0..r0+15
   for (int i = threadIdx.x; i < kv * B; i += kGramWG) Cs[i] = C1[i];
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  const int qx = li & 3, jq = li >> 2;
+  const int pull = 4 * ((4 * lk + qx) + 16 * jq);  // ds_bpermute byte address of the source lane
   f64x4 acc[G + 1];
 #pragma unroll
   for (int t = 0; t <= G; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
   const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t r_end = min(n, r_begin + rows_per_wg);
-  for (int64_t r0 = r_begin + wave * kGramRowsPerIter; r0 < r_end;
-       r0 += (kGramWG / 64) * kGramRowsPerIter) {
+  const int64_t last = r_end - 1;
+  // one 16-row group's loads: V in the update layout, W in the update's output
+  // layout (register reg: row r + 4 reg + lk, column li); rows clamped to the
+  // workgroup's last row (in bounds; such lanes are masked where used)
+  A v[G][4], w[4];
+  auto load_group = [&](int64_t r) {
+    const int64_t ra = min(r + li, last);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int c = 0; c < 4; c += VEC)
+        load_vec<T, VEC>(V + (int64_t)g * stride + ra * B + 4 * lk + c, v[g] + c);
+#pragma unroll
+    for (int reg = 0; reg < 4; ++reg)
+      w[reg] = (A)load_f64(W + min(r + 4 * reg + lk, last) * B + li);
+  };
+  int64_t r0 = r_begin + wave * kGramRowsPerIter;
+  if (r0 < r_end) load_group(r0);
+  for (; r0 < r_end; r0 += kStep) {
     asm volatile("" ::: "memory");  // keep the C1 reads inside the loop (no hoisting)
-    // V C1 for rows r0..r0+15 (row r0 + li clamped; rows past r_end not stored)
-    const int64_t ra = min(r0 + li, r_end - 1);
+    // V C1 for rows r0..r0+15
     f64x4 u = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      A v[4];
-      const T* vp = V + (int64_t)g * stride + ra * B + 4 * lk;
-#pragma unroll
-      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(vp + c, v + c);
+    for (int g = 0; g < G; ++g)
 #pragma unroll
       for (int st = 0; st < 4; ++st)
-        u = __builtin_amdgcn_mfma_f64_16x16x4f64((double)v[st], Cs[(16 * g + 4 * lk + st) * B + li],
-                                                 u, 0, 0, 0);
-    }
+        u = __builtin_amdgcn_mfma_f64_16x16x4f64((double)v[g][st],
+                                                 Cs[(16 * g + 4 * lk + st) * B + li], u, 0, 0, 0);
+    // this group's V in the Gram layout (before the quad transpose), and its W
+    A vg[G][4], wc[4];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) vg[g][c] = lane_pull(v[g][c], pull);
+#pragma unroll
+    for (int reg = 0; reg < 4; ++reg) wc[reg] = w[reg];
+    // the next group's loads (past r_end they re-read the last row and are unused)
+    load_group(r0 + kStep);
     // W' = W - V C1 in the output layout: register reg = row r0 + 4 reg + lk, column li
 #pragma unroll
     for (int reg = 0; reg < 4; ++reg) {
       const int64_t row = r0 + 4 * reg + lk;
       const bool rv = row < r_end;
-      const int64_t rc = rv ? row : r_end - 1;
-      const double d = load_f64(W + rc * B + li) - u[reg];
+      const double d = (double)wc[reg] - u[reg];
       const T t = to_storage<T, double>(d);
       double wr;
       if constexpr (sizeof(T) == 2)
         wr = (double)bf16_to_f32(t);
       else
         wr = (double)t;
-      if (rv) W[rc * B + li] = t;
+      if (rv) W[row * B + li] = t;
       Wt[wave][(4 * reg + lk) * 16 + li] = rv ? wr : 0.0;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // [V W']^T W' over the same rows in the Gram layout (lane (i, k) of step s:
-    // row 4k + s, column i), V as 16-byte column groups and a quad transpose
+    // row 4k + s, column i)
     double bw[4];
 #pragma unroll
     for (int st = 0; st < 4; ++st) bw[st] = Wt[wave][(4 * lk + st) * 16 + li];
-    const int qx = li & 3, jq = li >> 2;
-    const int64_t grow = r0 + 4 * lk + qx;  // the row this lane loads
-    const bool gv = grow < r_end;
-    const int64_t gb = (gv ? grow : r_end - 1) * B + 4 * jq;
+    const bool gv = r0 + 4 * lk + qx < r_end;  // the row this lane's vg holds
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      A v[4];
 #pragma unroll
-      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(V + (int64_t)g * stride + gb + c, v + c);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] = gv ? v[c] : (A)0;
-      quad_transpose(v, qx);
+      for (int c = 0; c < 4; ++c) vg[g][c] = gv ? vg[g][c] : (A)0;
+      quad_transpose(vg[g], qx);
 #pragma unroll
       for (int st = 0; st < 4; ++st)
-        acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)v[st], bw[st], acc[g], 0, 0, 0);
+        acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)vg[g][st], bw[st], acc[g], 0, 0, 0);
     }
 #pragma unroll
     for (int st = 0; st < 4; ++st)
@@ -489,12 +519,12 @@ __global__ __launch_bounds__(kGramWG) void cgs_mid16_kernel(const T* __restrict_
   }
   // wavefront partials added in wavefront order (deterministic)
   __shared__ double red[G + 1][4][64];
-  for (int w = 0; w < kGramWG / 64; ++w) {
-    if (wave == w) {
+  for (int w2 = 0; w2 < kGramWG / 64; ++w2) {
+    if (wave == w2) {
 #pragma unroll
       for (int t = 0; t <= G; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) red[t][r][lane] = (w == 0 ? 0.0 : red[t][r][lane]) + acc[t][r];
+        for (int r = 0; r < 4; ++r) red[t][r][lane] = (w2 == 0 ? 0.0 : red[t][r][lane]) + acc[t][r];
     }
     __syncthreads();
   }
@@ -549,7 +579,7 @@ __global__ __launch_bounds__(kGramWG) void gram16_kernel(const T* __restrict__ V
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int x = li & 3, jq = li >> 2;  // quad lane, quad: columns 4 jq .. 4 jq + 3
-  const int p_base = blockIdx.y * (16 * kGramPG);
+  const int p_base = blockIdx.y * (16 * NPG);  // slices of NPG whole 16-column blocks
   int64_t aoff[NPG];
   bool aval[NPG];
 #pragma unroll
@@ -563,42 +593,46 @@ __global__ __launch_bounds__(kGramWG) void gram16_kernel(const T* __restrict__ V
   for (int pg = 0; pg < NPG; ++pg) acc[pg] = f64x4{0.0, 0.0, 0.0, 0.0};
   const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t r_end = min(n, r_begin + rows_per_wg);
-  for (int64_t r0 = r_begin + wave * kGramRowsPerIter; r0 < r_end;
-       r0 += (kGramWG / 64) * kGramRowsPerIter) {
-    // each lane loads 4 consecutive columns of row r0 + 4 lk + x (clamped,
-    // masked afterwards); the quad transpose then gives lane (4 jq + x) column
-    // 4 jq + x of rows r0 + 4 lk + u, u = 0..3: the MFMA operands of steps u
-    const int64_t row = r0 + 4 * lk + x;
-    const bool rv = row < r_end;
-    const int64_t rb = (rv ? row : r_end - 1) * B;
-    double bw[4], a[4][NPG];
-    {
-      A w[4];
+  const int64_t last = r_end - 1;
+  constexpr int64_t kStep = (kGramWG / 64) * kGramRowsPerIter;
+  // each lane loads 4 consecutive columns of row r0 + 4 lk + x (clamped to the
+  // workgroup's last row, masked afterwards); the quad transpose then gives
+  // lane (4 jq + x) column 4 jq + x of rows r0 + 4 lk + u, u = 0..3: the MFMA
+  // operands of steps u.  The next group's loads are issued before this
+  // group's MFMAs.
+  A wr[4], vr[NPG][4];
+  auto load_group = [&](int64_t r) {
+    const int64_t rb = min(r + 4 * lk + x, last) * B;
 #pragma unroll
-      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(W + rb + 4 * jq + c, w + c);
+    for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(W + rb + 4 * jq + c, wr + c);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) w[c] = rv ? w[c] : (A)0;
-      quad_transpose(w, x);
+    for (int pg = 0; pg < NPG; ++pg)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) bw[u] = (double)w[u];
-    }
+      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(V + aoff[pg] + rb + c, vr[pg] + c);
+  };
+  int64_t r0 = r_begin + wave * kGramRowsPerIter;
+  if (r0 < r_end) load_group(r0);
+  for (; r0 < r_end; r0 += kStep) {
+    const bool rv = r0 + 4 * lk + x < r_end;
+    A w[4], v[NPG][4];
 #pragma unroll
-    for (int pg = 0; pg < NPG; ++pg) {
-      A v[4];
+    for (int c = 0; c < 4; ++c) w[c] = rv ? wr[c] : (A)0;
 #pragma unroll
-      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(V + aoff[pg] + rb + c, v + c);
-      const bool ok = rv && aval[pg];
+    for (int pg = 0; pg < NPG; ++pg)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] = ok ? v[c] : (A)0;
-      quad_transpose(v, x);
+      for (int c = 0; c < 4; ++c) v[pg][c] = (rv && aval[pg]) ? vr[pg][c] : (A)0;
+    load_group(r0 + kStep);  // past r_end: re-reads the last row, unused
+    quad_transpose(w, x);
+    double bw[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u][pg] = (double)v[u];
-    }
+    for (int u = 0; u < 4; ++u) bw[u] = (double)w[u];
+#pragma unroll
+    for (int pg = 0; pg < NPG; ++pg) quad_transpose(v[pg], x);
 #pragma unroll
     for (int st = 0; st < 4; ++st)
 #pragma unroll
       for (int pg = 0; pg < NPG; ++pg)
-        acc[pg] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][pg], bw[st], acc[pg], 0, 0, 0);
+        acc[pg] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)v[pg][st], bw[st], acc[pg], 0, 0, 0);
   }
   // wavefront partials added in wavefront order (deterministic)
   __shared__ double red[NPG][4][64];
@@ -643,8 +677,11 @@ fe_status gram_t(const void* V, int32_t nblk, int64_t stride, const void* W, int
 #define FE_GRAM2(KERNEL, Q, P)                                                                \
   hipLaunchKernelGGL((KERNEL<T, Q, P>), grid, dim3(kGramWG), 0, s, Vp, stride, Wp, n, b, k,   \
                      rows_per_wg, partials)
-  if (b == 16) {  // whole 16 x 16 MFMA tiles; zero V tiles past k
-    const int npg = std::min(kGramPG, (k + 15) / 16);
+  if (b == 16) {  // whole 16 x 16 MFMA tiles; the k / 16 tiles split evenly over the slices
+    const int tiles = (k + 15) / 16;
+    const int slices = (tiles + kGramPG - 1) / kGramPG;
+    const int npg = (tiles + slices - 1) / slices;
+    grid.y = slices;
     if (npg == 1) FE_GRAM(gram16_kernel, 1);
     else if (npg == 2) FE_GRAM(gram16_kernel, 2);
     else if (npg == 3) FE_GRAM(gram16_kernel, 3);
@@ -1529,6 +1566,35 @@ fe_status chol_second_launch(const double* G, int32_t b, const double* R1, doubl
                              double* recR, double* flag, hipStream_t s) {
   if (b > kCholMaxB) return fail(FE_EUNSUPPORTED, "chol: block %d > %d", b, kCholMaxB);
   hipLaunchKernelGGL(chol_second_kernel, dim3(1), dim3(256), 0, s, G, b, R1, M, recR, flag);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+// Z ((k + b) x b, row-major) = [-C2 M; M]: with it one right-multiplication
+// W <- [V W] Z applies the second Gram-Schmidt update (W - V C2) and the
+// inverse of the first Cholesky factor (M) together, one pass over [V W]
+// instead of an update pass and an in-place pass over W.
+__global__ __launch_bounds__(256) void cgs_coef_kernel(const double* __restrict__ C2,
+                                                       const double* __restrict__ M, int k, int b,
+                                                       double* __restrict__ Z) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < (k + b) * b; e += gridDim.x * blockDim.x) {
+    const int i = e / b, j = e % b;
+    double z;
+    if (i < k) {
+      double acc = 0.0;
+      for (int l = 0; l < b; ++l) acc = fma(C2[i * b + l], M[l * b + j], acc);
+      z = -acc;
+    } else {
+      z = M[(i - k) * b + j];
+    }
+    Z[e] = z;
+  }
+}
+
+fe_status cgs_coef_launch(const double* C2, const double* M, int32_t k, int32_t b, double* Z,
+                          hipStream_t s) {
+  const int cnt = (k + b) * b;
+  hipLaunchKernelGGL(cgs_coef_kernel, dim3((cnt + 255) / 256), dim3(256), 0, s, C2, M, k, b, Z);
   FE_HIP(hipGetLastError());
   return FE_OK;
 }

@@ -92,6 +92,10 @@ fe_status chol_first_launch(const double* C1, const double* C2, int32_t k, int32
                             double* rec, double* R1, double* M, double* flag, hipStream_t s);
 fe_status chol_second_launch(const double* G, int32_t b, const double* R1, double* M,
                              double* recR, double* flag, hipStream_t s);
+// Z ((k+b) x b) = [-C2 M; M] (C2: first k rows of the second Gram, M: b x b):
+// W <- [V W] Z is the second Gram-Schmidt update followed by W M in one pass.
+fe_status cgs_coef_launch(const double* C2, const double* M, int32_t k, int32_t b, double* Z,
+                          hipStream_t s);
 // W <- W - V C (C: k x b FP64, k = nblk*b <= 64, b in {1,2,4,8,16}) and, in
 // the same pass, Cout ((k+b) x b) = [V W']^T W' of the rounded result;
 // partials sized by gram_partials_doubles(n, k + b, b).

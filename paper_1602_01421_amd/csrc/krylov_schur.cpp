@@ -143,7 +143,8 @@ static size_t ks_workspace_plan(int64_t n, int nev, int b, int m, fe_dtype dt, b
   const size_t nblk = (size_t)(m / b + 1), kmax = (size_t)(m + b), stride = (size_t)n * b;
   const size_t d = sizeof(double);
   size_t t = ws_round(nblk * stride * es0);
-  t += ws_round(d * 2 * kmax * b) + ws_round(d * b * b) + ws_round(d * m * m);
+  t += ws_round(d * 2 * kmax * b) + ws_round(d * b * b) + ws_round(d * kmax * b) +
+       ws_round(d * m * m);
   t += ws_round(d * rotate_pad_doubles(m + b, std::max(m, 64)));
   t += ws_round(d * 64) + ws_round(d * 3 * 64);
   t += ws_round(d * gram_partials_doubles(n, (int32_t)kmax, b));
@@ -200,7 +201,7 @@ class Solver {
   int switch_restart = -1, spmm_low = 0;
   int64_t n, stride;
   char* V = nullptr;  // m/b + 1 blocks
-  double *dC = nullptr, *dM = nullptr, *dY = nullptr, *dYpad = nullptr, *dTheta = nullptr,
+  double *dC = nullptr, *dM = nullptr, *dZ = nullptr, *dY = nullptr, *dYpad = nullptr, *dTheta = nullptr,
          *dSums = nullptr;
   double *dPart = nullptr, *dPartRes = nullptr;
   double *hC1 = nullptr, *hC2 = nullptr, *hG = nullptr, *hM = nullptr, *hY = nullptr,
@@ -293,6 +294,7 @@ class Solver {
     const int kmax = m + b;
     FE_TRY(dev.get((void**)&dC, sizeof(double) * 2 * kmax * b));
     FE_TRY(dev.get((void**)&dM, sizeof(double) * b * b));
+    FE_TRY(dev.get((void**)&dZ, sizeof(double) * (m + b) * b));
     FE_TRY(dev.get((void**)&dY, sizeof(double) * m * m));
     FE_TRY(dev.get((void**)&dYpad, sizeof(double) * rotate_pad_doubles(m + b, std::max(m, 64))));
     FE_TRY(dev.get((void**)&dTheta, sizeof(double) * 64));
@@ -400,9 +402,16 @@ class Solver {
       FE_TRY(update(W, V, nk, dC1, -1.0, 1.0));
       FE_TRY(gram(nk + 1, W, dC2));
     }
-    FE_TRY(update(W, V, nk, dC2, -1.0, 1.0));
     FE_TRY(chol_first_launch(dC1, dC2, k, b, eta_chol, rec, dR1, dM, flag, s));
-    FE_TRY(update(W, W, 1, dM, 1.0, 0.0));
+    if (b >= 8) {
+      // W <- (W - V C2) R1^-1 as one in-place right-multiplication of [V W]
+      // (W is the block after V; each output row is written after its reads)
+      FE_TRY(cgs_coef_launch(dC2, dM, k, b, dZ, s));
+      FE_TRY(update(W, V, nk + 1, dZ, 1.0, 0.0));
+    } else {
+      FE_TRY(update(W, V, nk, dC2, -1.0, 1.0));
+      FE_TRY(update(W, W, 1, dM, 1.0, 0.0));
+    }
     prof.begin(P_GRAM);
     FE_TRY(gram_launch(W, 1, stride, W, n, b, dt, 1.0, dC, dPart, s));
     prof.end();
