@@ -119,6 +119,26 @@ def time_spmm(P, A, b, dtype, stream, reps):
     return [e0.elapsed_time(e1) * 1e-3 for e0, e1 in ev]
 
 
+def time_gather_bound(P, A, b, dtype, stream, reps):
+    """Per-launch durations (s) of the product's gathers alone (no rows):
+    fe_spmm_gather_bound on the same matrix and width, timed like time_spmm."""
+    import torch
+    X = torch.randn((A.n, b), device="cuda", dtype=torch.float32).to(dtype)
+    out = torch.empty(P.lib().fe_spmm_gather_bound_sets(), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            P.fe_spmm_gather_bound(A, X, out, stream=stream)
+        for e0, e1 in ev:
+            e0.record(stream)
+            P.fe_spmm_gather_bound(A, X, out, stream=stream)
+            e1.record(stream)
+    ev[-1][1].synchronize()
+    return [e0.elapsed_time(e1) * 1e-3 for e0, e1 in ev]
+
+
 def host_info():
     import platform
     import subprocess
@@ -406,6 +426,14 @@ def main():
             "launches": calls_dom, "avg_launch_us": t_dom / calls_dom * 1e6,
             "algorithmic_bytes_per_launch": b_dom / calls_dom,
             "stream_copy_gbs": stream_gbs, "frac_of_stream": achieved / stream_gbs}
+    if dom == "spmm":
+        # the product's own gathers, without rows: the memory system's ceiling
+        # for this index stream (the product also reads offsets and writes Y)
+        tg = float(np.median(time_gather_bound(P, A, block, torch.float32, stream, 10)))
+        roof["gather_bound_us"] = tg * 1e6
+        roof["gather_bound_frac"] = tg / (t_dom / calls_dom)
+        log(f"gathers alone at b={block}: {tg*1e3:.2f} ms per launch; the product "
+            f"{t_dom/calls_dom*1e3:.2f} ms ({100*roof['gather_bound_frac']:.0f}% of its ceiling)")
     spmm_alone = next((x for x in sweep if x["b"] == block), None)
 
     out = {

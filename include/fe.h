@@ -121,6 +121,20 @@ fe_status fe_spmm(const fe_csr *A, const void *X, void *Y, int32_t b, fe_dtype d
                   void *hip_stream);
 
 /*
+ * Measurement aid for fe_spmm's memory ceiling on this matrix: the same
+ * gathers without the rows.  Every stored column index, in storage order,
+ * fetches its row of X (n x b in dt, as in fe_spmm) in the same vector-wide
+ * chunks as fe_spmm; the values are summed per workgroup into out (device,
+ * fe_spmm_gather_bound_sets() doubles; their values carry no meaning beyond
+ * keeping the loads).  Its duration is what the product's gathers alone take
+ * (the product itself also reads row offsets, reduces rows and writes Y).
+ * Errors: FE_EINVAL (b out of range, NULL, misaligned X), FE_EDEVICE.
+ */
+fe_status fe_spmm_gather_bound(const fe_csr *A, const void *X, double *out, int32_t b,
+                               fe_dtype dt, void *hip_stream);
+int32_t fe_spmm_gather_bound_sets(void);
+
+/*
  * C = alpha * V^T W  (MvTransMv).  V: device, nblk >= 1 blocks of n x b, block
  * j at V + j*blk_stride elements (blk_stride >= n*b); W: device n x b.
  * C: device FP64, k x b row-major with k = nblk*b.  Arithmetic FP64; the sum

@@ -370,6 +370,18 @@ fe_status fe_spmm(const fe_csr* A, const void* X, void* Y, int32_t b, fe_dtype d
   return spmm_launch(*A, X, Y, b, dt, (hipStream_t)stream);
 }
 
+fe_status fe_spmm_gather_bound(const fe_csr* A, const void* X, double* out, int32_t b,
+                              fe_dtype dt, void* stream) {
+  if (!A || !X || !out) return fail(FE_EINVAL, "fe_spmm_gather_bound: NULL argument");
+  if (b < 1 || b > 64) return fail(FE_EINVAL, "fe_spmm_gather_bound: b=%d not in [1, 64]", b);
+  if (!dtype_ok(dt)) return fail(FE_EINVAL, "fe_spmm_gather_bound: bad dtype");
+  if (reinterpret_cast<uintptr_t>(X) % dtype_size(dt))
+    return fail(FE_EINVAL, "fe_spmm_gather_bound: X not aligned to the element size");
+  return gather_bound_launch(*A, X, out, b, dt, (hipStream_t)stream);
+}
+
+int32_t fe_spmm_gather_bound_sets(void) { return gather_bound_sets(); }
+
 static fe_status check_blocks(const char* fn, const void* V, int32_t nblk, int64_t stride,
                               int64_t n, int32_t b, fe_dtype dt) {
   if (!V) return fail(FE_EINVAL, "%s: V is NULL", fn);

@@ -1379,6 +1379,136 @@ fe_status cgs_mid_t(void* W, int64_t n, const void* V, int32_t nblk_v, int64_t s
   return FE_OK;
 }
 
+// The last pass of an orthogonalisation step at b = 16, in place:
+// W <- [V W] Z (Z: (16 NT) x 16, the second Gram-Schmidt update and the first
+// Cholesky factor's inverse together) and, from the rounded result, the
+// partials of W^T W for the second Cholesky factor.  NT = 16-column tiles of
+// [V W] (W the last); per 16-row group a wavefront forms the product in the
+// restart contraction's layout, stores it, and passes it through a 2 KB LDS
+// tile to the Gram layout as cgs_mid16_kernel does.  The next group's loads
+// are issued before this group's store and Gram.  Every row of W is read by
+// the wavefront that writes it, before it writes it.
+template <typename T, int NT>
+__global__ __launch_bounds__(kGramWG) void cgs_last16_kernel(T* V, int64_t stride, int64_t n,
+                                                             const double* __restrict__ Z,
+                                                             int64_t rows_per_wg,
+                                                             double* __restrict__ partials) {
+  using A = typename Acc<T>::type;
+  constexpr int VEC = 16 / sizeof(T) < 4 ? 16 / sizeof(T) : 4;
+  constexpr int B = 16;
+  constexpr int64_t kStep = (kGramWG / 64) * kGramRowsPerIter;
+  __shared__ double Zs[16 * NT * B];
+  __shared__ double Wt[kGramWG / 64][256];
+  for (int i = threadIdx.x; i < 16 * NT * B; i += kGramWG) Zs[i] = Z[i];
+  __syncthreads();
+  T* W = V + (int64_t)(NT - 1) * stride;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r_end = min(n, r_begin + rows_per_wg);
+  const int64_t last = r_end - 1;
+  A v[NT][4];
+  auto load_group = [&](int64_t r) {
+    const int64_t ra = min(r + li, last);
+#pragma unroll
+    for (int g = 0; g < NT; ++g)
+#pragma unroll
+      for (int c = 0; c < 4; c += VEC)
+        load_vec<T, VEC>(V + (int64_t)g * stride + ra * B + 4 * lk + c, v[g] + c);
+  };
+  int64_t r0 = r_begin + wave * kGramRowsPerIter;
+  if (r0 < r_end) load_group(r0);
+  for (; r0 < r_end; r0 += kStep) {
+    asm volatile("" ::: "memory");  // keep the Z reads inside the loop (no hoisting)
+    f64x4 u = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int g = 0; g < NT; ++g)
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+        u = __builtin_amdgcn_mfma_f64_16x16x4f64((double)v[g][st],
+                                                 Zs[(16 * g + 4 * lk + st) * B + li], u, 0, 0, 0);
+    load_group(r0 + kStep);  // past r_end: re-reads the last row, unused
+#pragma unroll
+    for (int reg = 0; reg < 4; ++reg) {
+      const int64_t row = r0 + 4 * reg + lk;
+      const bool rv = row < r_end;
+      const T t = to_storage<T, double>(u[reg]);
+      double wr;
+      if constexpr (sizeof(T) == 2)
+        wr = (double)bf16_to_f32(t);
+      else
+        wr = (double)t;
+      if (rv) W[row * B + li] = t;
+      Wt[wave][(4 * reg + lk) * 16 + li] = rv ? wr : 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double bw[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) bw[st] = Wt[wave][(4 * lk + st) * 16 + li];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bw[st], bw[st], acc, 0, 0, 0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // the tile's reads finish before the next rows' writes
+  }
+  // wavefront partials added in wavefront order (deterministic)
+  __shared__ double red[4][64];
+  for (int w2 = 0; w2 < kGramWG / 64; ++w2) {
+    if (wave == w2) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[r][lane] = (w2 == 0 ? 0.0 : red[r][lane]) + acc[r];
+    }
+    __syncthreads();
+  }
+  double* out = partials + (int64_t)blockIdx.x * B * B;
+  for (int idx = threadIdx.x; idx < 4 * 64; idx += kGramWG) {
+    const int l = idx & 63, r = idx >> 6;
+    out[(4 * r + (l >> 4)) * B + (l & 15)] = red[r][l];
+  }
+}
+
+template <typename T>
+fe_status cgs_last16_t(void* V, int32_t ntiles, int64_t stride, int64_t n, const double* Z,
+                       double* G, double* partials, hipStream_t s) {
+  const int gx = gram_sets(n);
+  int64_t rows_per_wg = (n + gx - 1) / gx;
+  rows_per_wg = (rows_per_wg + 15) / 16 * 16;
+  T* Vp = static_cast<T*>(V);
+#define FE_LAST16(NT)                                                                           \
+  case NT:                                                                                      \
+    hipLaunchKernelGGL((cgs_last16_kernel<T, NT>), dim3(gx), dim3(kGramWG), 0, s, Vp, stride, n, \
+                       Z, rows_per_wg, partials);                                               \
+    break;
+  switch (ntiles) {
+    FE_LAST16(2) FE_LAST16(3) FE_LAST16(4) FE_LAST16(5) FE_LAST16(6) FE_LAST16(7) FE_LAST16(8)
+    default:
+      return fail(FE_EUNSUPPORTED, "cgs_last: %d tiles at b = 16", ntiles);
+  }
+#undef FE_LAST16
+  FE_HIP(hipGetLastError());
+  hipLaunchKernelGGL(reduce_partials, dim3((256 + 63) / 64), dim3(1024), 0, s, partials, gx, 256,
+                     1.0, G);
+  FE_HIP(hipGetLastError());
+  return FE_OK;
+}
+
+bool cgs_last_supported(int32_t b, int32_t ntiles) { return b == 16 && ntiles >= 2 && ntiles <= 8; }
+
+fe_status cgs_last_launch(void* V, int32_t b, int32_t ntiles, int64_t stride, int64_t n,
+                          const double* Z, double* G, double* partials, fe_dtype dt,
+                          hipStream_t s) {
+  if (!cgs_last_supported(b, ntiles))
+    return fail(FE_EUNSUPPORTED, "cgs_last: b=%d with %d tiles", b, ntiles);
+  switch (dt) {
+    case FE_F64: return cgs_last16_t<double>(V, ntiles, stride, n, Z, G, partials, s);
+    case FE_F32: return cgs_last16_t<float>(V, ntiles, stride, n, Z, G, partials, s);
+    case FE_BF16: return cgs_last16_t<bf16_t>(V, ntiles, stride, n, Z, G, partials, s);
+  }
+  return fail(FE_EINVAL, "cgs_last: bad dtype");
+}
+
 bool cgs_mid_supported(int32_t b, int32_t nblk_v) {
   if (b == 4) return nblk_v >= 1 && nblk_v * 4 + 4 <= 128;
   if (b == 16) return nblk_v >= 1 && nblk_v * 16 + 16 <= 128;

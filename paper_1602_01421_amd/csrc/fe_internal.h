@@ -75,6 +75,11 @@ fe_status csr_upload(Csr* A, std::vector<int64_t>&& row_ptr, std::vector<int32_t
 
 fe_status spmm_launch(const Csr& A, const void* X, void* Y, int32_t b, fe_dtype dt,
                       hipStream_t s);
+// The product's gathers without its rows (a measurement of its memory
+// ceiling on this matrix): out gets gather_bound_sets() FP64 workgroup sums.
+int32_t gather_bound_sets();
+fe_status gather_bound_launch(const Csr& A, const void* X, double* out, int32_t b, fe_dtype dt,
+                              hipStream_t s);
 
 // ------------------------------------------------------------- dense side
 // partial buffer size (doubles) needed by gram_launch, update_gram_launch and
@@ -107,6 +112,13 @@ fe_status update_gram_launch(void* W, int64_t n, int32_t b, const void* V, int32
 // n x b block, not overlapping V).  Up to 128 columns of [V W]
 // (cgs_mid_supported); partials as for gram_launch.
 bool cgs_mid_supported(int32_t b, int32_t nblk_v);
+// The last pass of an orthogonalisation step at b = 16, in place: W <- [V W] Z
+// (ntiles = blocks of [V W], W the last; Z (16 ntiles) x 16 FP64) and
+// G = W^T W (16 x 16) of the rounded result; partials as for gram_launch.
+bool cgs_last_supported(int32_t b, int32_t ntiles);
+fe_status cgs_last_launch(void* V, int32_t b, int32_t ntiles, int64_t blk_stride, int64_t n,
+                          const double* Z, double* G, double* partials, fe_dtype dt,
+                          hipStream_t s);
 fe_status cgs_mid_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk_v,
                          int64_t blk_stride, const double* C1, double* Cout, double* partials,
                          fe_dtype dt, hipStream_t s);

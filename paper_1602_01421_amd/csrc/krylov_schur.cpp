@@ -403,6 +403,19 @@ class Solver {
       FE_TRY(gram(nk + 1, W, dC2));
     }
     FE_TRY(chol_first_launch(dC1, dC2, k, b, eta_chol, rec, dR1, dM, flag, s));
+    if (cgs_last_supported(b, nk + 1)) {
+      // W <- (W - V C2) R1^-1 as one in-place right-multiplication of [V W]
+      // (W is the block after V), with W^T W of the result in the same pass
+      FE_TRY(cgs_coef_launch(dC2, dM, k, b, dZ, s));
+      prof.begin(P_UPDATE);
+      FE_TRY(cgs_last_launch(V, b, nk + 1, stride, n, dZ, dC, dPart, dt, s));
+      prof.end();
+      ++update_calls;
+      ++gram_calls;
+      bytes[P_UPDATE] += (double)n * b * es * (nk + 2);  // [V W] read, W written
+      FE_TRY(chol_second_launch(dC, b, dR1, dM, rec + (size_t)m * b, flag, s));
+      return update(W, W, 1, dM, 1.0, 0.0);
+    }
     if (b >= 8) {
       // W <- (W - V C2) R1^-1 as one in-place right-multiplication of [V W]
       // (W is the block after V; each output row is written after its reads)

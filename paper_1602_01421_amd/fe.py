@@ -22,7 +22,8 @@ FE_SYMMETRIZE, FE_DEDUPE, FE_DROP_SELF, FE_RELABEL_BY_DEGREE = 0x1, 0x2, 0x4, 0x
 FE_GRAPH_DEFAULT = FE_SYMMETRIZE | FE_DEDUPE | FE_DROP_SELF
 
 EXPORTED = ("fe_last_error", "fe_version", "fe_csr_build", "fe_csr_from_csr", "fe_csr_info",
-            "fe_csr_perm", "fe_csr_export", "fe_csr_free", "fe_spmm", "fe_gram", "fe_gram_noalloc",
+            "fe_csr_perm", "fe_csr_export", "fe_csr_free", "fe_spmm", "fe_spmm_gather_bound",
+            "fe_spmm_gather_bound_sets", "fe_gram", "fe_gram_noalloc",
             "fe_block_update", "fe_block_update_gram", "fe_krylov_schur", "fe_ks_workspace_bytes",
             "fe_svds",
             "fe_dense_symeig", "fe_gnn_param_count",
@@ -84,6 +85,7 @@ def lib():
             "fe_csr_perm": [P, P],
             "fe_csr_export": [P, P, P],
             "fe_spmm": [P, P, P, i32, i32, P],
+            "fe_spmm_gather_bound": [P, P, P, i32, i32, P],
             "fe_gram": [P, i32, i64, P, i64, i32, i32, f64, P, P],
             "fe_gram_noalloc": [P, i32, i64, P, i64, i32, i32, f64, P, P],
             "fe_block_update": [P, i64, i32, P, i32, i64, P, f64, f64, i32, P],
@@ -112,6 +114,8 @@ def lib():
         L.fe_gnn_free.restype = None
         L.fe_gnn_param_count.argtypes = []
         L.fe_gnn_param_count.restype = i64
+        L.fe_spmm_gather_bound_sets.argtypes = []
+        L.fe_spmm_gather_bound_sets.restype = i32
         _lib = L
     return _lib
 
@@ -223,6 +227,23 @@ def fe_spmm(A: Csr, X, Y=None, stream=None):
         Y = torch.empty_like(X)
     _check(lib().fe_spmm(A.handle, _dev_ptr(X), _dev_ptr(Y), X.shape[1], _dt_of(X), _stream(stream)))
     return Y
+
+
+def fe_spmm_gather_bound(A: Csr, X, out=None, stream=None):
+    """The product's gathers without its rows (its memory ceiling on A): X (n, b)
+    device tensor; out: FP64 device buffer of fe_spmm_gather_bound_sets()
+    workgroup sums (allocated if None); returns out."""
+    import torch
+    if X.dim() != 2 or X.shape[0] != A.n:
+        raise FeError(FE_EINVAL, f"X must be ({A.n}, b)")
+    sets = lib().fe_spmm_gather_bound_sets()
+    if out is None:
+        out = torch.empty(sets, dtype=torch.float64, device=X.device)
+    if out.dtype != torch.float64 or out.numel() < sets:
+        raise FeError(FE_EINVAL, f"out must hold {sets} float64")
+    _check(lib().fe_spmm_gather_bound(A.handle, _dev_ptr(X), _dev_ptr(out), X.shape[1], _dt_of(X),
+                                      _stream(stream)))
+    return out
 
 
 def fe_gram(V, W, alpha: float = 1.0, C=None, stream=None):

@@ -193,3 +193,24 @@ def test_spmm_rmat22_sampled_rows(fe, b):
     absum = O.spmm_rows_from_edges(n, s, d, np.abs(Xq), old_rows[order])
     got = Y[new_rows][order]
     assert np.all(np.abs(got - want) <= 1e-5 * absum + 1e-30)
+
+
+@pytest.mark.parametrize("name", ["rmat14", "star40k", "cycle1001"])
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("b", [1, 3, 16])
+def test_gather_bound_touches_every_stored_nonzero(fe, name, dt, b):
+    """The measurement kernel (the product's gathers without its rows) sums the
+    X row of every stored nonzero exactly once: on small integers its total is
+    exactly the oracle product's total."""
+    A, rp, ci = built(fe, name, True)
+    X = S.small_ints((A.n, b), seed=5, lo=-3, hi=3)
+    perm = A.perm()
+    out = fe.fe_spmm_gather_bound(A, to_dev(X[perm], DT[dt]))
+    assert out.numel() == fe.lib().fe_spmm_gather_bound_sets()
+    assert float(out.sum().item()) == float(O.spmm(rp, ci, X).sum())
+
+
+def test_gather_bound_empty_matrix(fe):
+    A = fe.fe_csr_build(10, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    out = fe.fe_spmm_gather_bound(A, torch.ones((10, 4), dtype=torch.float32, device="cuda"))
+    assert torch.count_nonzero(out) == 0
