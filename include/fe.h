@@ -135,6 +135,16 @@ fe_status fe_spmm_gather_bound(const fe_csr *A, const void *X, double *out, int3
 int32_t fe_spmm_gather_bound_sets(void);
 
 /*
+ * The same gathers over a caller's index stream, to measure what another
+ * order of the product's gathers would cost: X row idx[e] (device int32,
+ * count entries, clamped to [0, n)) for e = 0 .. count-1 in order, X device
+ * n x b in dt; out as for fe_spmm_gather_bound.
+ * Errors: FE_EINVAL (NULL, sizes, b out of range, misaligned X), FE_EDEVICE.
+ */
+fe_status fe_gather_rows(const int32_t *idx, int64_t count, const void *X, int64_t n, int32_t b,
+                         fe_dtype dt, double *out, void *hip_stream);
+
+/*
  * C = alpha * V^T W  (MvTransMv).  V: device, nblk >= 1 blocks of n x b, block
  * j at V + j*blk_stride elements (blk_stride >= n*b); W: device n x b.
  * C: device FP64, k x b row-major with k = nblk*b.  Arithmetic FP64; the sum

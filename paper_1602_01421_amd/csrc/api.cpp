@@ -382,6 +382,17 @@ fe_status fe_spmm_gather_bound(const fe_csr* A, const void* X, double* out, int3
 
 int32_t fe_spmm_gather_bound_sets(void) { return gather_bound_sets(); }
 
+fe_status fe_gather_rows(const int32_t* idx, int64_t count, const void* X, int64_t n, int32_t b,
+                         fe_dtype dt, double* out, void* stream) {
+  if (!X || !out || (count > 0 && !idx)) return fail(FE_EINVAL, "fe_gather_rows: NULL argument");
+  if (count < 0 || n < 1) return fail(FE_EINVAL, "fe_gather_rows: bad sizes");
+  if (b < 1 || b > 64) return fail(FE_EINVAL, "fe_gather_rows: b=%d not in [1, 64]", b);
+  if (!dtype_ok(dt)) return fail(FE_EINVAL, "fe_gather_rows: bad dtype");
+  if (reinterpret_cast<uintptr_t>(X) % dtype_size(dt))
+    return fail(FE_EINVAL, "fe_gather_rows: X not aligned to the element size");
+  return gather_rows_launch(idx, count, true, X, n, out, b, dt, (hipStream_t)stream);
+}
+
 static fe_status check_blocks(const char* fn, const void* V, int32_t nblk, int64_t stride,
                               int64_t n, int32_t b, fe_dtype dt) {
   if (!V) return fail(FE_EINVAL, "%s: V is NULL", fn);

@@ -32,6 +32,7 @@ namespace {
 constexpr int kGramWG = 512;          // 8 wavefronts
 constexpr int kGramRowsPerIter = 16;  // rows per wavefront per iteration (4 MFMA steps)
 constexpr int kGramPG = 4;            // 16-column V groups per workgroup (64 V columns)
+constexpr int kCgsWG = 256;           // cgs_last16_kernel: 4 wavefronts
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename T, int NQG>
@@ -659,6 +660,14 @@ int gram_sets(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(512, by_rows));
 }
 
+// Row intervals of cgs_last16_kernel: four-wavefront workgroups over twice as
+// many intervals as the Gram's (measured a little faster there; the middle
+// step, at up to ~180 VGPRs, was slower in this shape and keeps the Gram's).
+int cgs_sets(int64_t n) {
+  int64_t by_rows = (n + 4 * kGramRowsPerIter - 1) / (4 * kGramRowsPerIter);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(1024, by_rows));
+}
+
 template <typename T>
 fe_status gram_t(const void* V, int32_t nblk, int64_t stride, const void* W, int64_t n, int32_t b,
                  double alpha, double* C, double* partials, hipStream_t s) {
@@ -678,14 +687,23 @@ fe_status gram_t(const void* V, int32_t nblk, int64_t stride, const void* W, int
   hipLaunchKernelGGL((KERNEL<T, Q, P>), grid, dim3(kGramWG), 0, s, Vp, stride, Wp, n, b, k,   \
                      rows_per_wg, partials)
   if (b == 16) {  // whole 16 x 16 MFMA tiles; the k / 16 tiles split evenly over the slices
+    // up to 8 tiles per slice for 4- and 2-byte storage (one pass over W up to
+    // 128 columns), 4 for FP64 (register-bound)
+    constexpr int max_pg = sizeof(T) <= 4 ? 8 : kGramPG;
     const int tiles = (k + 15) / 16;
-    const int slices = (tiles + kGramPG - 1) / kGramPG;
+    const int slices = (tiles + max_pg - 1) / max_pg;
     const int npg = (tiles + slices - 1) / slices;
     grid.y = slices;
     if (npg == 1) FE_GRAM(gram16_kernel, 1);
     else if (npg == 2) FE_GRAM(gram16_kernel, 2);
     else if (npg == 3) FE_GRAM(gram16_kernel, 3);
-    else FE_GRAM(gram16_kernel, 4);
+    else if (npg == 4) FE_GRAM(gram16_kernel, 4);
+    else if constexpr (max_pg == 8) {
+      if (npg == 5) FE_GRAM(gram16_kernel, 5);
+      else if (npg == 6) FE_GRAM(gram16_kernel, 6);
+      else if (npg == 7) FE_GRAM(gram16_kernel, 7);
+      else FE_GRAM(gram16_kernel, 8);
+    }
   } else if (b % 4 == 0) {  // 16-byte row loads and quad transposes
     // NPG: 16-column V groups per slice, a template parameter so that no MFMA
     // chain is guarded (groups past k are fed zeros)
@@ -1292,7 +1310,7 @@ size_t rotate_pad_doubles(int32_t m, int32_t p) {
 
 // ------------------------------------------------------------- launchers
 size_t gram_partials_doubles(int64_t n, int32_t k, int32_t b) {
-  return (size_t)std::max(gram_sets(n), ug_sets(n)) * (size_t)k * (size_t)b;
+  return (size_t)std::max({gram_sets(n), ug_sets(n), cgs_sets(n)}) * (size_t)k * (size_t)b;
 }
 
 size_t gram_sets_partials_doubles(int64_t n, int32_t k, int32_t b) {
@@ -1389,17 +1407,17 @@ fe_status cgs_mid_t(void* W, int64_t n, const void* V, int32_t nblk_v, int64_t s
 // are issued before this group's store and Gram.  Every row of W is read by
 // the wavefront that writes it, before it writes it.
 template <typename T, int NT>
-__global__ __launch_bounds__(kGramWG) void cgs_last16_kernel(T* V, int64_t stride, int64_t n,
+__global__ __launch_bounds__(kCgsWG) void cgs_last16_kernel(T* V, int64_t stride, int64_t n,
                                                              const double* __restrict__ Z,
                                                              int64_t rows_per_wg,
                                                              double* __restrict__ partials) {
   using A = typename Acc<T>::type;
   constexpr int VEC = 16 / sizeof(T) < 4 ? 16 / sizeof(T) : 4;
   constexpr int B = 16;
-  constexpr int64_t kStep = (kGramWG / 64) * kGramRowsPerIter;
+  constexpr int64_t kStep = (kCgsWG / 64) * kGramRowsPerIter;
   __shared__ double Zs[16 * NT * B];
-  __shared__ double Wt[kGramWG / 64][256];
-  for (int i = threadIdx.x; i < 16 * NT * B; i += kGramWG) Zs[i] = Z[i];
+  __shared__ double Wt[kCgsWG / 64][256];
+  for (int i = threadIdx.x; i < 16 * NT * B; i += kCgsWG) Zs[i] = Z[i];
   __syncthreads();
   T* W = V + (int64_t)(NT - 1) * stride;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1455,7 +1473,7 @@ __global__ __launch_bounds__(kGramWG) void cgs_last16_kernel(T* V, int64_t strid
   }
   // wavefront partials added in wavefront order (deterministic)
   __shared__ double red[4][64];
-  for (int w2 = 0; w2 < kGramWG / 64; ++w2) {
+  for (int w2 = 0; w2 < kCgsWG / 64; ++w2) {
     if (wave == w2) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) red[r][lane] = (w2 == 0 ? 0.0 : red[r][lane]) + acc[r];
@@ -1463,7 +1481,7 @@ __global__ __launch_bounds__(kGramWG) void cgs_last16_kernel(T* V, int64_t strid
     __syncthreads();
   }
   double* out = partials + (int64_t)blockIdx.x * B * B;
-  for (int idx = threadIdx.x; idx < 4 * 64; idx += kGramWG) {
+  for (int idx = threadIdx.x; idx < 4 * 64; idx += kCgsWG) {
     const int l = idx & 63, r = idx >> 6;
     out[(4 * r + (l >> 4)) * B + (l & 15)] = red[r][l];
   }
@@ -1472,13 +1490,13 @@ __global__ __launch_bounds__(kGramWG) void cgs_last16_kernel(T* V, int64_t strid
 template <typename T>
 fe_status cgs_last16_t(void* V, int32_t ntiles, int64_t stride, int64_t n, const double* Z,
                        double* G, double* partials, hipStream_t s) {
-  const int gx = gram_sets(n);
+  const int gx = cgs_sets(n);
   int64_t rows_per_wg = (n + gx - 1) / gx;
   rows_per_wg = (rows_per_wg + 15) / 16 * 16;
   T* Vp = static_cast<T*>(V);
 #define FE_LAST16(NT)                                                                           \
   case NT:                                                                                      \
-    hipLaunchKernelGGL((cgs_last16_kernel<T, NT>), dim3(gx), dim3(kGramWG), 0, s, Vp, stride, n, \
+    hipLaunchKernelGGL((cgs_last16_kernel<T, NT>), dim3(gx), dim3(kCgsWG), 0, s, Vp, stride, n, \
                        Z, rows_per_wg, partials);                                               \
     break;
   switch (ntiles) {

@@ -80,6 +80,9 @@ fe_status spmm_launch(const Csr& A, const void* X, void* Y, int32_t b, fe_dtype 
 int32_t gather_bound_sets();
 fe_status gather_bound_launch(const Csr& A, const void* X, double* out, int32_t b, fe_dtype dt,
                               hipStream_t s);
+// The same gathers over a caller's index stream (clamp: indices clamped to [0, n)).
+fe_status gather_rows_launch(const int32_t* idx, int64_t count, bool clamp, const void* X,
+                             int64_t n, double* out, int32_t b, fe_dtype dt, hipStream_t s);
 
 // ------------------------------------------------------------- dense side
 // partial buffer size (doubles) needed by gram_launch, update_gram_launch and

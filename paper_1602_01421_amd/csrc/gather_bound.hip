@@ -4,7 +4,8 @@
 // product (CPAD lanes per row, consecutive lanes on consecutive nonzeros, the
 // index stream read non-temporally), and the sums are only reduced per
 // workgroup.  Its time is what the product's gathers alone cost on this
-// matrix.
+// matrix.  The same kernel over a caller's index stream measures what another
+// order of the same gathers would cost.
 #include "dev_common.h"
 #include "fe_internal.h"
 
@@ -14,10 +15,13 @@ namespace {
 constexpr int kWG = 256;
 constexpr int kGatherSets = 16384;
 
-template <typename T, int VEC, int CPAD>
+// CLAMP: indices from a caller's stream are clamped to [0, n) (the product's own
+// column indices are valid by construction).
+template <typename T, int VEC, int CPAD, bool CLAMP>
 __global__ __launch_bounds__(kWG) void gather_bound_kernel(const int32_t* __restrict__ col,
                                                            int64_t nnz, const T* __restrict__ X,
-                                                           int32_t b, double* __restrict__ out) {
+                                                           int32_t b, int64_t n,
+                                                           double* __restrict__ out) {
   using A = typename Acc<T>::type;
   constexpr int U = 8;
   constexpr int SLOTS = kWG / CPAD;
@@ -36,6 +40,10 @@ __global__ __launch_bounds__(kWG) void gather_bound_kernel(const int32_t* __rest
         j[u] = __builtin_nontemporal_load(col + (q < nnz ? q : nnz - 1));
       }
       A v[U][VEC];
+      if constexpr (CLAMP) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) j[u] = j[u] < 0 ? 0 : ((int64_t)j[u] >= n ? (int32_t)(n - 1) : j[u]);
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) load_vec<T, VEC>(Xc + (int64_t)j[u] * b, v[u]);
 #pragma unroll
@@ -60,7 +68,8 @@ __global__ __launch_bounds__(kWG) void gather_bound_kernel(const int32_t* __rest
 }
 
 template <typename T>
-fe_status gather_bound_t(const Csr& A, const void* X, double* out, int32_t b, hipStream_t s) {
+fe_status gather_bound_t(const int32_t* idx, int64_t count, bool clamp, const void* X, int64_t n,
+                         double* out, int32_t b, hipStream_t s) {
   constexpr int maxvec = 16 / sizeof(T);
   int vec = 1;
   const uintptr_t align = reinterpret_cast<uintptr_t>(X);
@@ -70,8 +79,12 @@ fe_status gather_bound_t(const Csr& A, const void* X, double* out, int32_t b, hi
   const T* Xp = static_cast<const T*>(X);
 #define FE_GB(V, C)                                                                          \
   if (vec == V && cpad == C) {                                                               \
-    hipLaunchKernelGGL((gather_bound_kernel<T, V, C>), dim3(kGatherSets), dim3(kWG), 0, s,   \
-                       A.d_col, A.nnz, Xp, b, out);                                          \
+    if (clamp)                                                                               \
+      hipLaunchKernelGGL((gather_bound_kernel<T, V, C, true>), dim3(kGatherSets), dim3(kWG),  \
+                         0, s, idx, count, Xp, b, n, out);                                   \
+    else                                                                                     \
+      hipLaunchKernelGGL((gather_bound_kernel<T, V, C, false>), dim3(kGatherSets), dim3(kWG), \
+                         0, s, idx, count, Xp, b, n, out);                                   \
     FE_HIP(hipGetLastError());                                                               \
     return FE_OK;                                                                            \
   }
@@ -87,14 +100,19 @@ fe_status gather_bound_t(const Csr& A, const void* X, double* out, int32_t b, hi
 
 int32_t gather_bound_sets() { return kGatherSets; }
 
-fe_status gather_bound_launch(const Csr& A, const void* X, double* out, int32_t b, fe_dtype dt,
-                              hipStream_t s) {
-  switch (dt) {  // nnz == 0: every workgroup writes 0
-    case FE_F64: return gather_bound_t<double>(A, X, out, b, s);
-    case FE_F32: return gather_bound_t<float>(A, X, out, b, s);
-    case FE_BF16: return gather_bound_t<bf16_t>(A, X, out, b, s);
+fe_status gather_rows_launch(const int32_t* idx, int64_t count, bool clamp, const void* X,
+                             int64_t n, double* out, int32_t b, fe_dtype dt, hipStream_t s) {
+  switch (dt) {  // count == 0: every workgroup writes 0
+    case FE_F64: return gather_bound_t<double>(idx, count, clamp, X, n, out, b, s);
+    case FE_F32: return gather_bound_t<float>(idx, count, clamp, X, n, out, b, s);
+    case FE_BF16: return gather_bound_t<bf16_t>(idx, count, clamp, X, n, out, b, s);
   }
   return fail(FE_EINVAL, "gather bound: bad dtype");
+}
+
+fe_status gather_bound_launch(const Csr& A, const void* X, double* out, int32_t b, fe_dtype dt,
+                              hipStream_t s) {
+  return gather_rows_launch(A.d_col, A.nnz, false, X, A.n, out, b, dt, s);
 }
 
 }  // namespace fe

@@ -23,7 +23,7 @@ FE_GRAPH_DEFAULT = FE_SYMMETRIZE | FE_DEDUPE | FE_DROP_SELF
 
 EXPORTED = ("fe_last_error", "fe_version", "fe_csr_build", "fe_csr_from_csr", "fe_csr_info",
             "fe_csr_perm", "fe_csr_export", "fe_csr_free", "fe_spmm", "fe_spmm_gather_bound",
-            "fe_spmm_gather_bound_sets", "fe_gram", "fe_gram_noalloc",
+            "fe_spmm_gather_bound_sets", "fe_gather_rows", "fe_gram", "fe_gram_noalloc",
             "fe_block_update", "fe_block_update_gram", "fe_krylov_schur", "fe_ks_workspace_bytes",
             "fe_svds",
             "fe_dense_symeig", "fe_gnn_param_count",
@@ -86,6 +86,7 @@ def lib():
             "fe_csr_export": [P, P, P],
             "fe_spmm": [P, P, P, i32, i32, P],
             "fe_spmm_gather_bound": [P, P, P, i32, i32, P],
+            "fe_gather_rows": [P, i64, P, i64, i32, i32, P, P],
             "fe_gram": [P, i32, i64, P, i64, i32, i32, f64, P, P],
             "fe_gram_noalloc": [P, i32, i64, P, i64, i32, i32, f64, P, P],
             "fe_block_update": [P, i64, i32, P, i32, i64, P, f64, f64, i32, P],
@@ -243,6 +244,23 @@ def fe_spmm_gather_bound(A: Csr, X, out=None, stream=None):
         raise FeError(FE_EINVAL, f"out must hold {sets} float64")
     _check(lib().fe_spmm_gather_bound(A.handle, _dev_ptr(X), _dev_ptr(out), X.shape[1], _dt_of(X),
                                       _stream(stream)))
+    return out
+
+
+def fe_gather_rows(idx, X, out=None, stream=None):
+    """The product's gathers over an index stream: X row idx[e] for every e, in
+    order (idx: 1-D int32 device tensor; X: (n, b) device tensor); out as for
+    fe_spmm_gather_bound; returns out."""
+    import torch
+    if X.dim() != 2 or idx.dim() != 1 or idx.dtype != torch.int32:
+        raise FeError(FE_EINVAL, "idx must be 1-D int32 and X (n, b)")
+    sets = lib().fe_spmm_gather_bound_sets()
+    if out is None:
+        out = torch.empty(sets, dtype=torch.float64, device=X.device)
+    if out.dtype != torch.float64 or out.numel() < sets:
+        raise FeError(FE_EINVAL, f"out must hold {sets} float64")
+    _check(lib().fe_gather_rows(_dev_ptr(idx), idx.numel(), _dev_ptr(X), X.shape[0], X.shape[1],
+                                _dt_of(X), _dev_ptr(out), _stream(stream)))
     return out
 
 

@@ -173,25 +173,35 @@ def large(args):
     A, info = build_rmat(F, args.scale)
     out = {"study": "large", "graph": f"rmat{args.scale}", "n": A.n, "nnz": A.nnz,
            "max_deg": A.max_deg, **info, "spmm": [], "configs": []}
-    for b in sorted({int(c.split("x")[0]) for c in args.configs.split(",")}):
+    shapes = [parse_shape(c) for c in args.configs.split(",")]
+    for b in sorted({sh[0] for sh in shapes}):
         x = time_spmm(F, A, b, torch.float32, reps=args.spmm_reps)
         out["spmm"].append(x)
         _log(f"[study] product b={b} FP32: {x['ms']:.2f} ms, {x['gedge_col_s']:.0f} GEdge*col/s, "
              f"{x['gbs']:.0f} GB/s ({100 * x['frac']:.1f}% of 8 TB/s)")
     gc.collect()
     torch.cuda.empty_cache()
-    for c in args.configs.split(","):
-        b, m = (int(v) for v in c.split("x"))
-        out["configs"].append(large_config(F, A, args, 8, b, m))
+    for b, m, keep in shapes:
+        out["configs"].append(large_config(F, A, args, 8, b, m, keep))
     print(json.dumps(out), flush=True)
 
 
-def large_config(F, A, args, nev, b, m):
+def parse_shape(c):
+    """BLOCKxM or BLOCKxMkKEEP (KEEP: Ritz vectors kept at a restart, 0 = the
+    library's default)."""
+    b, rest = c.split("x")
+    m, _, keep = rest.partition("k")
+    return int(b), int(m), int(keep or 0)
+
+
+def large_config(F, A, args, nev, b, m, keep=0):
     """Solves of one shape.  With --seeds S: random starts from seeds 1..S and,
     for every weights file, S draws of the network's random inputs."""
     from .learned import START_CHECK, START_DROP, learned_start
+    import functools
     import torch
-    _log(f"[study] configuration nev {nev}, block {b}, m {m}")
+    _log(f"[study] configuration nev {nev}, block {b}, m {m}, keep {keep or 'default'}")
+    run_solve = functools.partial(_run_solve_keep, keep)
     mr = args.max_restarts
     runs = set(args.runs.split(","))
     seeds = list(range(1, max(1, args.seeds) + 1))
@@ -244,7 +254,11 @@ def large_config(F, A, args, nev, b, m):
                     rows.append(row)
                 del X
                 torch.cuda.empty_cache()
-    return {"nev": nev, "block": b, "m": m, "max_restarts": mr, "solves": rows}
+    return {"nev": nev, "block": b, "m": m, "keep": keep, "max_restarts": mr, "solves": rows}
+
+
+def _run_solve_keep(keep, F, A, label, ref=None, **kw):
+    return run_solve(F, A, label, ref, keep=keep, **kw)
 
 
 def gnn(args):
@@ -335,27 +349,34 @@ def svd(args):
 
 
 def ops(args):
+    """The tall-and-skinny operations alone at n rows, block width b, for basis
+    sizes m (multiples of b): Gram V^T W, the block update W - V C (at b = 8
+    and 16 the MFMA contraction) and, at b = 4 and 16 with m + b <= 128, the
+    fused CGS2 middle step (W - V C and [V W]^T W in one pass)."""
     from . import fe as F
     import torch
-    n, b = args.n, 4
+    n, b = args.n, args.b
     out = {"study": "ops", "n": n, "b": b, "rows": []}
     g = torch.Generator(device="cuda")
     g.manual_seed(3)
     for dt in (torch.float32, torch.float64):
         es = torch.tensor([], dtype=dt).element_size()
         for m in [int(x) for x in args.ms.split(",")]:
-            if dt == torch.float64 and m > args.f64_max_m:
+            if (dt == torch.float64 and m > args.f64_max_m) or m % b:
                 continue
             nblk = m // b
             V = torch.randn((nblk, n, b), generator=g, device="cuda", dtype=torch.float32).to(dt)
             W = torch.randn((n, b), generator=g, device="cuda", dtype=torch.float32).to(dt)
             C = torch.randn((m, b), generator=g, device="cuda", dtype=torch.float64) * 1e-3
-            G = torch.empty((m, b), dtype=torch.float64, device="cuda")
+            G = torch.empty((m + b, b), dtype=torch.float64, device="cuda")
             res = {"dtype": str(dt).replace("torch.", ""), "m": m}
-            for name, fn, byts, flops in (
-                    ("gram", lambda: F.fe_gram(V, W, C=G), n * (m + b) * es, 2.0 * n * m * b),
-                    ("update", lambda: F.fe_block_update(W, V, C), n * (m + 2 * b) * es,
-                     2.0 * n * m * b)):
+            cases = [("gram", lambda: F.fe_gram(V, W, C=G[:m]), n * (m + b) * es, 2.0 * n * m * b),
+                     ("update", lambda: F.fe_block_update(W, V, C), n * (m + 2 * b) * es,
+                      2.0 * n * m * b)]
+            if b in (4, 16) and m + b <= 128:
+                cases.append(("cgs_mid", lambda: F.fe_block_update_gram(W, V, C, Cout=G),
+                              n * (m + 2 * b) * es, 2.0 * n * (2 * m + b) * b))
+            for name, fn, byts, flops in cases:
                 for _ in range(3):
                     fn()
                 ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -369,13 +390,76 @@ def ops(args):
                 res[name] = {"ms": t * 1e3, "gbs": byts / t / 1e9,
                              "frac": byts / t / 1e9 / HBM_PEAK_GBS, "tflops": flops / t / 1e12}
             out["rows"].append(res)
-            _log(f"[study] ops {res['dtype']} m={m:3d}: gram {res['gram']['ms']:8.2f} ms "
-                 f"{res['gram']['gbs']:7.0f} GB/s ({100 * res['gram']['frac']:.0f}%), update "
-                 f"{res['update']['ms']:8.2f} ms {res['update']['gbs']:7.0f} GB/s "
-                 f"({100 * res['update']['frac']:.0f}%)")
+            _log(f"[study] ops {res['dtype']} b={b} m={m:3d}: " + ", ".join(
+                f"{k} {v['ms']:8.2f} ms {v['gbs']:6.0f} GB/s ({100 * v['frac']:.0f}%) "
+                f"{v['tflops']:5.1f} TFLOP/s" for k, v in res.items() if isinstance(v, dict)))
             del V, W, C, G
             torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
+
+
+def gathers(args):
+    """The product's gather ceiling on R-MAT: the product, its gathers alone in
+    storage order, and the hub rows' gathers (degree > --hub) re-ordered column
+    band by column band (row order kept within a band), for band widths of
+    2^shift columns: whether visiting the matrix tile by tile, so that each
+    band's slice of X stays in cache, would make the gathers cheaper."""
+    from . import fe as F
+    import torch
+    A, info = build_rmat(F, args.scale)
+    n, nnz, b = A.n, A.nnz, args.b
+    X = torch.randn((n, b), device="cuda", dtype=torch.float32)
+    Y = torch.empty_like(X)
+    out = torch.empty(F.lib().fe_spmm_gather_bound_sets(), dtype=torch.float64, device="cuda")
+
+    def tm(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for e0, e1 in ev:
+            e0.record()
+            fn()
+            e1.record()
+        torch.cuda.synchronize()
+        return float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+
+    res = {"study": "gathers", "graph": f"rmat{args.scale}", "n": n, "nnz": nnz, "b": b, **info,
+           "product_ms": tm(lambda: F.fe_spmm(A, X, Y)),
+           "gathers_storage_order_ms": tm(lambda: F.fe_spmm_gather_bound(A, X, out))}
+    _log(f"[study] product {res['product_ms']:.2f} ms, its gathers alone "
+         f"{res['gathers_storage_order_ms']:.2f} ms")
+    rp, ci = A.export()
+    A.close()
+    del Y
+    deg = np.diff(rp)
+    hubs = int((deg > args.hub).sum())
+    eh = int(rp[hubs])
+    hub = torch.from_numpy(ci[:eh]).cuda()
+    rest = torch.from_numpy(ci[eh:]).cuda()
+    del ci, rp
+    res.update({"hub_degree": args.hub, "hub_rows": hubs, "hub_nonzeros": eh,
+                "hub_row_order_ms": tm(lambda: F.fe_gather_rows(hub, X, out)),
+                "other_rows_ms": tm(lambda: F.fe_gather_rows(rest, X, out)), "bands": []})
+    _log(f"[study] hub rows ({hubs}, {eh / nnz:.3f} of the nonzeros): {res['hub_row_order_ms']:.2f} ms;"
+         f" the others {res['other_rows_ms']:.2f} ms")
+    del rest
+    chunks = [hub[i:i + (1 << 30)] for i in range(0, hub.numel(), 1 << 30)]
+    for shift in [int(x) for x in args.shifts.split(",")]:
+        nb = (n + (1 << shift) - 1) >> shift
+        keys = [c >> shift for c in chunks]
+        parts = [torch.masked_select(c, k == band) for band in range(nb) for c, k in zip(chunks, keys)]
+        del keys
+        banded = torch.cat(parts)
+        del parts
+        t = tm(lambda: F.fe_gather_rows(banded, X, out))
+        del banded
+        torch.cuda.empty_cache()
+        mib = (1 << shift) * b * 4 / 2 ** 20
+        res["bands"].append({"columns_per_band": 1 << shift, "bands": nb, "x_slice_mib": mib, "ms": t})
+        _log(f"[study] hub rows band by band, {nb} bands of {1 << shift} columns "
+             f"({mib:.0f} MiB of X each): {t:.2f} ms")
+    print(json.dumps(res), flush=True)
 
 
 def main():
@@ -390,7 +474,8 @@ def main():
     q = sub.add_parser("large")
     q.add_argument("--scale", type=int, default=27)
     q.add_argument("--configs", default="8x48",
-                   help="comma list of BLOCKxM solve shapes, all nev 8 (e.g. 8x48,4x64)")
+                   help="comma list of BLOCKxM[kKEEP] solve shapes, all nev 8 (e.g. 8x48,"
+                        "4x64,8x48k16: KEEP Ritz vectors kept at each restart)")
     q.add_argument("--max-restarts", type=int, default=500)
     q.add_argument("--weights", default=None, help="comma list of learned-start weight files")
     q.add_argument("--seeds", type=int, default=1,
@@ -411,10 +496,17 @@ def main():
     v.add_argument("--max-restarts", type=int, default=500)
     o = sub.add_parser("ops")
     o.add_argument("--n", type=int, default=60_000_000)
+    o.add_argument("--b", type=int, default=4, help="block width")
     o.add_argument("--ms", default="4,8,16,32,64,128,256,512")
     o.add_argument("--f64-max-m", type=int, default=256)
     o.add_argument("--reps", type=int, default=5)
-    for sp in (p, q, r, v, o):
+    w = sub.add_parser("gathers")
+    w.add_argument("--scale", type=int, default=27)
+    w.add_argument("--b", type=int, default=16)
+    w.add_argument("--hub", type=int, default=2048, help="hub rows: degree above this")
+    w.add_argument("--shifts", default="24,22,20,18,16",
+                   help="band widths as powers of two of columns")
+    for sp in (p, q, r, v, o, w):
         sp.add_argument("--verbose", action="store_true",
                         help="one line per restart from the solver (stderr)")
     args = ap.parse_args()
@@ -422,7 +514,8 @@ def main():
     VERBOSE = args.verbose
     import torch
     torch.cuda.set_device(0)
-    {"precision": precision, "large": large, "gnn": gnn, "svd": svd, "ops": ops}[args.cmd](args)
+    {"precision": precision, "large": large, "gnn": gnn, "svd": svd, "ops": ops,
+     "gathers": gathers}[args.cmd](args)
 
 
 if __name__ == "__main__":

@@ -214,3 +214,18 @@ def test_gather_bound_empty_matrix(fe):
     A = fe.fe_csr_build(10, np.zeros(0, np.int32), np.zeros(0, np.int32))
     out = fe.fe_spmm_gather_bound(A, torch.ones((10, 4), dtype=torch.float32, device="cuda"))
     assert torch.count_nonzero(out) == 0
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f64"])
+def test_gather_rows_over_a_given_stream(fe, dt):
+    """fe_gather_rows sums X row idx[e] for every entry of the stream; indices
+    outside [0, n) are clamped to it."""
+    n, b = 5000, 16
+    X = S.small_ints((n, b), seed=9, lo=-3, hi=3)
+    rng = np.random.default_rng(4)
+    idx = rng.integers(-50, n + 50, 200_003).astype(np.int32)
+    out = fe.fe_gather_rows(torch.from_numpy(idx).cuda(), to_dev(X, DT[dt]))
+    want = X[np.clip(idx, 0, n - 1)].sum()
+    assert float(out.sum().item()) == float(want)
+    empty = fe.fe_gather_rows(torch.zeros(0, dtype=torch.int32, device="cuda"), to_dev(X, DT[dt]))
+    assert torch.count_nonzero(empty) == 0

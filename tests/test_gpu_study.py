@@ -59,3 +59,20 @@ def test_gnn_driver_small(fe, capsys):
     assert d["n"] == 4096 and d["params"] == 19136
     for mode in ("bf16", "f32"):
         assert all(d[mode][k] > 0 for k in ("forward_ms", "train_step_ms", "adam_ms"))
+
+
+def test_gathers_driver_small(fe, capsys):
+    from paper_1602_01421_amd import study
+    d = run(capsys, study.gathers, scale=12, b=16, hub=64, shifts="10,8")
+    assert d["n"] == 4096 and d["hub_rows"] > 0 and 0 < d["hub_nonzeros"] < d["nnz"]
+    assert [x["columns_per_band"] for x in d["bands"]] == [1024, 256]
+    assert d["product_ms"] > 0 and d["gathers_storage_order_ms"] > 0
+
+
+def test_large_driver_restart_size(fe, capsys):
+    from paper_1602_01421_amd import study
+    d = run(capsys, study.large, scale=12, configs="8x48k16", runs="f32", max_restarts=500,
+            weights=None, spmm_reps=3, seeds=1)
+    cfg = d["configs"][0]
+    assert (cfg["block"], cfg["m"], cfg["keep"]) == (8, 48, 16)
+    assert cfg["solves"][0]["status"] == 0
