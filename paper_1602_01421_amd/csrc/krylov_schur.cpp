@@ -646,6 +646,35 @@ class Solver {
     return FE_OK;
   }
 
+  // The start block (no basis yet).  Its Gram matrix decides first: with every
+  // column's ratio (Schur complement of the Gram matrix over its diagonal) at
+  // least eta_chol, Cholesky QR twice runs on the device, which is what the
+  // careful path settles on for such a block; otherwise (a dependent, nearly
+  // dependent or non-finite column) the careful path runs.  For a random or
+  // learned block this replaces 16 column-by-column passes over the block by
+  // four.
+  fe_status orth_start(std::vector<double>& C, std::vector<double>& R) {
+    void* W = blk(0);
+    double* rec = dRec;  // block 0's record: R at m b, the flag after it
+    double* flag = rec + (size_t)m * b + (size_t)b * b;
+    double* hflag = hRec + (size_t)m * b + (size_t)b * b;
+    FE_TRY(gram(1, W, dC));
+    FE_TRY(chol_first_launch(dC, dC, 0, b, eta_chol, rec, dR1, dM, flag, s));
+    FE_HIP(hipMemcpyAsync(hflag, flag, sizeof(double), hipMemcpyDeviceToHost, s));
+    FE_TRY(sync());
+    if (*hflag != 0.0) return orth_block(0, C, R);
+    FE_TRY(update(W, W, 1, dM, 1.0, 0.0));
+    FE_TRY(gram(1, W, dC));
+    FE_TRY(chol_second_launch(dC, b, dR1, dM, rec + (size_t)m * b, flag, s));
+    FE_HIP(hipMemcpyAsync(hflag, flag, sizeof(double), hipMemcpyDeviceToHost, s));
+    FE_TRY(sync());
+    if (*hflag != 0.0) return orth_block(0, C, R);  // W R1^-1 spans the same space
+    FE_TRY(update(W, W, 1, dM, 1.0, 0.0));
+    C.clear();
+    R.assign((size_t)b * b, 0.0);  // the start block's factor is not used
+    return FE_OK;
+  }
+
   fe_status run(double* evals, void* evecs, fe_ks_report* rep) {
     auto t0 = clk::now();
     FE_TRY(setup());
@@ -674,7 +703,7 @@ class Solver {
     prof.end();
     std::vector<double> C, R;
     step = 0;
-    FE_TRY(orth_block(0, C, R));
+    FE_TRY(orth_start(C, R));
     int k = 0;  // basis columns; Q is block k/b
     int restarts = 0;
     std::vector<double> theta(m), Y((size_t)m * m), rho(m);
@@ -800,7 +829,7 @@ class Solver {
           std::fill(T.begin(), T.end(), 0.0);
           std::fill(Bk.begin(), Bk.end(), 0.0);
           step = 0;
-          FE_TRY(orth_block(0, C, R));
+          FE_TRY(orth_start(C, R));
           k = 0;
           ++restarts;
           continue;
@@ -819,7 +848,7 @@ class Solver {
           switch_restart = restarts;
           std::fill(T.begin(), T.end(), 0.0);
           std::fill(Bk.begin(), Bk.end(), 0.0);
-          FE_TRY(orth_block(0, C, R));
+          FE_TRY(orth_start(C, R));
           k = 0;
           ++restarts;
           continue;
