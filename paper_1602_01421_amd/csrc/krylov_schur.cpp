@@ -68,17 +68,18 @@ struct Prof {
   double t[4] = {0, 0, 0, 0};
   int open_cls = -1;
   hipEvent_t open_a = nullptr;
-  void begin(int cls) {
+  // st: the stream the timed work runs on (default: the solve's stream)
+  void begin(int cls, hipStream_t st = nullptr) {
     if (!on) return;
     hipEventCreate(&open_a);
-    hipEventRecord(open_a, s);
+    hipEventRecord(open_a, st ? st : s);
     open_cls = cls;
   }
-  void end() {
+  void end(hipStream_t st = nullptr) {
     if (!on || open_cls < 0) return;
     hipEvent_t e;
     hipEventCreate(&e);
-    hipEventRecord(e, s);
+    hipEventRecord(e, st ? st : s);
     recs.push_back({open_cls, open_a, e});
     open_cls = -1;
   }
@@ -154,6 +155,7 @@ static size_t ks_workspace_plan(int64_t n, int nev, int b, int m, fe_dtype dt, b
   if (mixed && start) t += ws_round(stride * esf);
   if (mixed) t += ws_round(nblk * stride * esf) + ws_round(d * stride);
   t += 2 * ws_round(d * (size_t)n * nev);
+  t += ws_round(stride * std::max(es0, esf));  // the restart overlap's spare block
   return t;
 }
 
@@ -189,6 +191,13 @@ class Solver {
   const Csr& A;
   const Csr* At = nullptr;  // set for the singular value problem: the operator is A^T A
   void* Tb = nullptr;       // n x b block between the two products (A^T A)
+  // Restart overlap: the next expansion's first product (from Q, which the
+  // rotation neither reads nor writes) runs on a second stream into `spare`
+  // while the restart rotation runs on the solve's stream.
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  void* spare = nullptr;
+  bool pre_product = false;
   double* T64 = nullptr;    // n x nev FP64, the final check's A X (A^T A)
   int nev, b, m;
   double tol, eta, eta_chol;
@@ -236,6 +245,14 @@ class Solver {
       dev.arena = static_cast<char*>(o.workspace);
       dev.arena_bytes = o.workspace_bytes;
     }
+  }
+  ~Solver() {
+    if (s2) {
+      (void)hipStreamSynchronize(s2);  // before the buffers it may still use are freed
+      (void)hipStreamDestroy(s2);
+    }
+    if (ev_a) (void)hipEventDestroy(ev_a);
+    if (ev_b) (void)hipEventDestroy(ev_b);
   }
 
   // eta: refill threshold on the column-wise ratio (reading: 1e-10 for FP64
@@ -313,6 +330,10 @@ class Solver {
     FE_TRY(host.get(&hRec, rec_stride * (m / b + 1)));
     FE_TRY(dev.get((void**)&dR1, sizeof(double) * b * b));
     if (At) FE_TRY(dev.get(&Tb, (size_t)n * b * std::max(es, dtype_size(dt_final))));
+    FE_TRY(dev.get(&spare, (size_t)n * b * std::max(es, dtype_size(dt_final))));
+    FE_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+    FE_HIP(hipEventCreateWithFlags(&ev_a, hipEventDisableTiming));
+    FE_HIP(hipEventCreateWithFlags(&ev_b, hipEventDisableTiming));
     T.assign((size_t)m * m, 0.0);
     Bk.assign((size_t)b * m, 0.0);
     return FE_OK;
@@ -344,11 +365,12 @@ class Solver {
     bytes[P_UPDATE] += (double)n * b * es * ((in_place ? 0 : nblk) + (beta != 0.0 || in_place) + 1);
     return st;
   }
-  fe_status spmm(const void* X, void* Y, int cols) {
-    prof.begin(P_SPMM);
-    fe_status st = At ? spmm_launch(A, X, Tb, cols, dt, s) : spmm_launch(A, X, Y, cols, dt, s);
-    if (st == FE_OK && At) st = spmm_launch(*At, Tb, Y, cols, dt, s);
-    prof.end();
+  fe_status spmm(const void* X, void* Y, int cols) { return spmm_on(X, Y, cols, s); }
+  fe_status spmm_on(const void* X, void* Y, int cols, hipStream_t st_) {
+    prof.begin(P_SPMM, st_);
+    fe_status st = At ? spmm_launch(A, X, Tb, cols, dt, st_) : spmm_launch(A, X, Y, cols, dt, st_);
+    if (st == FE_OK && At) st = spmm_launch(*At, Tb, Y, cols, dt, st_);
+    prof.end(st_);
     spmm_cols += cols;
     bytes[P_SPMM] += (At ? 2.0 : 1.0) * (4.0 * A.nnz + 8.0 * (n + 1) + 2.0 * n * cols * es);
     return st;
@@ -732,7 +754,10 @@ class Solver {
           k += b;
           const int wb = k / b;
           const int step0 = step;
-          FE_TRY(spmm(blk(wb - 1), blk(wb), b));
+          if (pre_product)  // computed during the restart rotation
+            pre_product = false;
+          else
+            FE_TRY(spmm(blk(wb - 1), blk(wb), b));
           ++spmm_calls;
           if (dt != dt_final) ++spmm_low;
           ++step;
@@ -859,10 +884,20 @@ class Solver {
       for (int i = 0; i < m; ++i)
         for (int j = 0; j < p; ++j) hY[(size_t)i * p + j] = Y[(size_t)i * m + j];
       FE_HIP(hipMemcpyAsync(dY, hY, sizeof(double) * m * p, hipMemcpyHostToDevice, s));
+      // the next expansion's first product A Q (Q = block m/b, which the
+      // rotation neither reads nor writes) on the second stream, into the
+      // spare block, while the rotation runs here
+      FE_HIP(hipEventRecord(ev_a, s));
+      FE_HIP(hipStreamWaitEvent(s2, ev_a, 0));
+      FE_TRY(spmm_on(blk(m / b), spare, b, s2));
+      FE_HIP(hipEventRecord(ev_b, s2));
       prof.begin(P_OTHER);
       FE_TRY(rotate_launch(V, n, b, m / b, p / b, stride, dY, dYpad, dt, s));
       FE_TRY(copy_block(blk(p / b), blk(m / b), n, b, dt, s));
+      FE_HIP(hipStreamWaitEvent(s, ev_b, 0));
+      FE_TRY(copy_block(blk(p / b + 1), spare, n, b, dt, s));
       prof.end();
+      pre_product = true;
       std::vector<double> Bn((size_t)b * m, 0.0);
       for (int i = 0; i < b; ++i)
         for (int j = 0; j < p; ++j) {
