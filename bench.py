@@ -438,6 +438,12 @@ def main():
         log(f"gathers alone at b={block}: {tg*1e3:.2f} ms per launch; the product "
             f"{t_dom/calls_dom*1e3:.2f} ms ({100*roof['gather_bound_frac']:.0f}% of its ceiling)")
     spmm_alone = next((x for x in sweep if x["b"] == block), None)
+    if dom == "spmm" and spmm_alone:
+        # the same kernel alone (the sweep's launches at this width): in the
+        # solve the first product after each restart shares the GPU with the
+        # restart rotation, which lengthens those launches
+        roof["standalone_launch_us"] = spmm_alone["us"]
+        roof["frac_standalone"] = b_dom / calls_dom / (spmm_alone["us"] * 1e-6) / 1e9 / HBM_PEAK_GBS
 
     out = {
         "metric": METRIC, "value": value, "unit": "GEdge·col/s", "n_gpus": 1,
