@@ -438,6 +438,8 @@ def main():
         log(f"gathers alone at b={block}: {tg*1e3:.2f} ms per launch; the product "
             f"{t_dom/calls_dom*1e3:.2f} ms ({100*roof['gather_bound_frac']:.0f}% of its ceiling)")
     spmm_alone = next((x for x in sweep if x["b"] == block), None)
+    if roof["traffic"]:
+        roof["traffic_gbs"] = roof["traffic"] / (t_dom / calls_dom) / 1e9  # bytes beyond the L2
     if dom == "spmm" and spmm_alone:
         # the same kernel alone (the sweep's launches at this width): in the
         # solve the first product after each restart shares the GPU with the
