@@ -306,11 +306,14 @@ typedef struct {
  * descending, ties to the larger theta); evecs (device n x nev in opts->dt,
  * original vertex order, 2-norm 1 up to storage rounding) or NULL; rep (host)
  * or NULL.
- * Device memory: (m + block) * n elements of dt (mixed: of BF16, then from
+ * Device memory: (m + 2 block) * n elements of dt (mixed: of BF16, then from
  * the switch of dt, with n * block doubles during the switch), 2 * nev * n
  * doubles and small FP64 buffers; allocated for the call and freed before
  * return, or carved from opts->workspace (fe_ks_workspace_bytes gives the
- * size).  Synchronises the stream before returning.
+ * size).  The solve also runs work on a second stream of its own (created
+ * and destroyed by the call, default priority): at each restart the next
+ * expansion's first product overlaps the restart rotation, which touches
+ * other blocks.  Synchronises the stream before returning.
  * Errors: FE_EINVAL (also a workspace smaller than fe_ks_workspace_bytes or
  * not 256-byte aligned), FE_ENOMEM, FE_EDEVICE, FE_ENOCONV (max_restarts reached;
  * outputs hold the current estimates), FE_EUNSUPPORTED (sizes beyond the limits).
