@@ -75,7 +75,7 @@ def test_round_bf16_specials():
 
 # ------------------------------------------------------------ restart size
 @pytest.mark.parametrize("m,b,nev,p", [(32, 4, 8, 20), (48, 4, 8, 28), (48, 8, 8, 32), (64, 8, 8, 40)])
-def test_restart_keep_survey_values(m, b, nev, p):
+def test_restart_keep_reading_values(m, b, nev, p):
     assert O.restart_keep(m, b, nev) == p
 
 
