@@ -406,3 +406,37 @@ def test_restart_size_option_matches_oracle(fe, keep):
         with pytest.raises(fe.FeError) as e:
             fe.fe_krylov_schur(A, 8, 4, 32, 1e-10, dtype=torch.float64, keep=bad)
         assert e.value.status == fe.FE_EINVAL
+
+
+@pytest.mark.parametrize("n", [301, 4099])
+def test_block16_ragged_rows_fp64_match_oracle(fe, n):
+    """Block 16 at row counts off the 16-row group and the row intervals of
+    the fused CGS2 kernels (middle step, last step with its Gram) and of the
+    start block's device Cholesky QR: FP64 storage, same start block as the
+    oracle: same products, eigenvalues within 1e-10."""
+    g = S.chung_lu_edges(n, alpha=2.2, mean_deg=12, seed=23)
+    A, rp, ci = setup(fe, g)
+    X0 = S.normal((A.n, 16), seed=9)
+    ref = oracle_ks(rp, ci, A.n, 8, 16, 64, 1e-9, X0)
+    r = fe.fe_krylov_schur(A, 8, 16, 64, 1e-9, dtype=torch.float64,
+                           start=torch.tensor(X0, device="cuda"))
+    assert r.status == fe.FE_OK and ref.converged
+    assert np.allclose(r.evals, ref.evals, rtol=1e-10, atol=0)
+    assert r.spmm_calls == ref.spmm_calls
+    check_vectors(rp, ci, r)
+
+
+def test_block16_small_graph_against_dense_eigh(fe):
+    """n = 90 with block 16, m 64 (the subspace nearly fills the space, so
+    dependent columns and refills occur): the 8 largest-magnitude
+    eigenvalues of the dense matrix."""
+    n, s, d = S.chung_lu_edges(90, alpha=2.2, mean_deg=10, seed=5)
+    A, rp, ci = setup(fe, (n, s, d))
+    D = np.zeros((n, n))
+    for i in range(n):
+        D[i, ci[rp[i]:rp[i + 1]]] = 1.0
+    w = np.linalg.eigvalsh(D)
+    want = w[np.argsort(-np.abs(w), kind="stable")][:8]
+    r = fe.fe_krylov_schur(A, 8, 16, 64, 1e-10, dtype=torch.float64, seed=4)
+    assert r.status == fe.FE_OK
+    assert np.allclose(np.sort(r.evals), np.sort(want), rtol=1e-9, atol=1e-9)
