@@ -444,6 +444,18 @@ def gathers(args):
     _log(f"[study] hub rows ({hubs}, {eh / nnz:.3f} of the nonzeros): {res['hub_row_order_ms']:.2f} ms;"
          f" the others {res['other_rows_ms']:.2f} ms")
     del rest
+    # the same number of gathers from uniformly random rows, and from one row
+    # (every gather a cache hit): the memory system's ends for this row size
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    idx = torch.randint(0, n, (nnz,), generator=g, device="cuda", dtype=torch.int32)
+    res["uniform_random_ms"] = tm(lambda: F.fe_gather_rows(idx, X, out))
+    idx.zero_()
+    res["one_row_ms"] = tm(lambda: F.fe_gather_rows(idx, X, out))
+    del idx
+    torch.cuda.empty_cache()
+    _log(f"[study] {nnz} gathers from uniformly random rows {res['uniform_random_ms']:.2f} ms, "
+         f"from one row {res['one_row_ms']:.2f} ms")
     chunks = [hub[i:i + (1 << 30)] for i in range(0, hub.numel(), 1 << 30)]
     for shift in [int(x) for x in args.shifts.split(",")]:
         nb = (n + (1 << shift) - 1) >> shift
