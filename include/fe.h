@@ -201,10 +201,10 @@ fe_status fe_block_update(void *W, int64_t n, int32_t b, const void *V, int32_t 
  *                            b rows W^T W)
  * Equal to fe_block_update (alpha -1, beta 1) followed by fe_gram over the
  * nblk blocks plus W, up to the order of the FP64 sums.  V and W as in
- * fe_gram; W must not overlap V.  At b = 4 and b = 16 with k + b <= 128 the
- * solver's register-resident kernels run (W, V and the block stride then
- * aligned to min(16, 4 x element size) bytes); otherwise an LDS-tiled kernel
- * with k <= 64.
+ * fe_gram; W must not overlap V.  At b = 4, 8 and 16 with k + b <= 128 (at
+ * b = 8 in FP64: k <= 96) the solver's register-resident kernels run (W, V
+ * and the block stride then aligned to min(16, 4 x element size) bytes);
+ * otherwise an LDS-tiled kernel with k <= 64.
  * Errors: FE_EINVAL (sizes, NULL, overlap, alignment), FE_EUNSUPPORTED (b not
  * in {1,2,4,8,16}, or k beyond those limits), FE_ENOMEM, FE_EDEVICE.
  */

@@ -446,7 +446,7 @@ fe_status fe_block_update_gram(void* W, int64_t n, int32_t b, const void* V, int
                                void* stream) {
   FE_TRY(check_blocks("fe_block_update_gram", V, nblk, stride, n, b, dt));
   if (!W || !C || !Cout) return fail(FE_EINVAL, "fe_block_update_gram: NULL argument");
-  const bool fused = cgs_mid_supported(b, nblk);
+  const bool fused = cgs_mid_supported(b, nblk, dt);
   if (!fused && (!(b == 1 || b == 2 || b == 4 || b == 8 || b == 16) || nblk * b > 64))
     return fail(FE_EUNSUPPORTED,
                 "fe_block_update_gram: needs b in {1,2,4,8,16} and k <= 64 (k + b <= 128 at b = 4, 16)");

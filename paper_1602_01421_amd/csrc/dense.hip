@@ -416,21 +416,26 @@ __device__ __forceinline__ double lane_pull(double v, int src4) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename T, int G>
+// B = 16: G basis blocks, one 16-column tile each.  B = 8: kv = 8 nblk_v
+// basis columns in G = ceil(nblk_v / 2) tiles (tile g = blocks 2g and
+// 2g + 1, the second absent when nblk_v is odd); W's 8 columns fill half of
+// each 16 x 16 MFMA tile, the other half is fed zeros.
+template <typename T, int G, int B>
 __global__ __launch_bounds__(kGramWG) void cgs_mid16_kernel(const T* __restrict__ V,
                                                             int64_t stride, T* __restrict__ W,
-                                                            int64_t n,
+                                                            int64_t n, int32_t kv,
                                                             const double* __restrict__ C1,
                                                             int64_t rows_per_wg,
                                                             double* __restrict__ partials) {
   using A = typename Acc<T>::type;
   constexpr int VEC = 16 / sizeof(T) < 4 ? 16 / sizeof(T) : 4;
-  constexpr int B = 16;
-  constexpr int kv = 16 * G, k = kv + B;
+  static_assert(B == 8 || B == 16, "cgs_mid16: b = 8 or 16");
+  if constexpr (B == 16) kv = 16 * G;  // a compile-time constant there
+  const int k = kv + B;
   constexpr int64_t kStep = (kGramWG / 64) * kGramRowsPerIter;
-  __shared__ double Cs[kv * B];          // C1 (kv x 16)
+  __shared__ double Cs[16 * G * B];      // C1 (kv x B), zero rows up to 16 G
   __shared__ double Wt[kGramWG / 64][256];  // per wavefront: W' rows r0..r0+15
-  for (int i = threadIdx.x; i < kv * B; i += kGramWG) Cs[i] = C1[i];
+  for (int i = threadIdx.x; i < 16 * G * B; i += kGramWG) Cs[i] = i < kv * B ? C1[i] : 0.0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -445,17 +450,28 @@ __global__ __launch_bounds__(kGramWG) void cgs_mid16_kernel(const T* __restrict_
   // one 16-row group's loads: V in the update layout, W in the update's output
   // layout (register reg: row r + 4 reg + lk, column li); rows clamped to the
   // workgroup's last row (in bounds; such lanes are masked where used)
+  // this lane's four columns 16 g + 4 lk .. + 3 of tile g: block and offset
+  // (columns past kv, B = 8 only, read block 0 and meet zero rows of Cs; their
+  // Gram rows are not written)
+  auto voff = [&](int g) -> int64_t {
+    if constexpr (B == 16) {
+      return (int64_t)g * stride + 4 * lk;
+    } else {
+      const int c = 16 * g + 4 * lk;
+      return c < kv ? (int64_t)(2 * g + (lk >> 1)) * stride + 4 * (lk & 1) : 0;
+    }
+  };
+  const int lw = li < B ? li : 0;  // W column of this lane (B = 8: lanes 8..15 idle)
   A v[G][4], w[4];
   auto load_group = [&](int64_t r) {
     const int64_t ra = min(r + li, last);
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
-      for (int c = 0; c < 4; c += VEC)
-        load_vec<T, VEC>(V + (int64_t)g * stride + ra * B + 4 * lk + c, v[g] + c);
+      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(V + voff(g) + ra * B + c, v[g] + c);
 #pragma unroll
     for (int reg = 0; reg < 4; ++reg)
-      w[reg] = (A)load_f64(W + min(r + 4 * reg + lk, last) * B + li);
+      w[reg] = (A)load_f64(W + min(r + 4 * reg + lk, last) * B + lw);
   };
   int64_t r0 = r_begin + wave * kGramRowsPerIter;
   if (r0 < r_end) load_group(r0);
@@ -467,8 +483,8 @@ __global__ __launch_bounds__(kGramWG) void cgs_mid16_kernel(const T* __restrict_
     for (int g = 0; g < G; ++g)
 #pragma unroll
       for (int st = 0; st < 4; ++st)
-        u = __builtin_amdgcn_mfma_f64_16x16x4f64((double)v[g][st],
-                                                 Cs[(16 * g + 4 * lk + st) * B + li], u, 0, 0, 0);
+        u = __builtin_amdgcn_mfma_f64_16x16x4f64(
+            (double)v[g][st], li < B ? Cs[(16 * g + 4 * lk + st) * B + lw] : 0.0, u, 0, 0, 0);
     // this group's V in the Gram layout (before the quad transpose), and its W
     A vg[G][4], wc[4];
 #pragma unroll
@@ -491,8 +507,8 @@ __global__ __launch_bounds__(kGramWG) void cgs_mid16_kernel(const T* __restrict_
         wr = (double)bf16_to_f32(t);
       else
         wr = (double)t;
-      if (rv) W[row * B + li] = t;
-      Wt[wave][(4 * reg + lk) * 16 + li] = rv ? wr : 0.0;
+      if (rv && li < B) W[row * B + li] = t;
+      Wt[wave][(4 * reg + lk) * 16 + li] = (rv && li < B) ? wr : 0.0;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -532,8 +548,9 @@ __global__ __launch_bounds__(kGramWG) void cgs_mid16_kernel(const T* __restrict_
   double* out = partials + (int64_t)blockIdx.x * k * B;
   for (int idx = threadIdx.x; idx < (G + 1) * 4 * 64; idx += kGramWG) {
     const int l = idx & 63, r = (idx >> 6) & 3, t = idx >> 8;
-    const int p = 16 * t + 4 * r + (l >> 4), q = l & 15;
-    out[(int64_t)p * B + q] = red[t][r][l];
+    const int i = 4 * r + (l >> 4), q = l & 15;  // row of the 16 x 16 tile, column
+    const int p = t < G ? 16 * t + i : kv + i;    // V rows, then W's
+    if (q < B && (t < G ? p < kv : i < B)) out[(int64_t)p * B + q] = red[t][r][l];
   }
 }
 
@@ -1340,24 +1357,36 @@ fe_status gram_launch(const void* V, int32_t nblk, int64_t stride, const void* W
 }
 
 template <typename T>
-fe_status cgs_mid16_t(void* W, int64_t n, const void* V, int32_t nblk_v, int64_t stride,
+fe_status cgs_mid16_t(void* W, int64_t n, int32_t b, const void* V, int32_t nblk_v, int64_t stride,
                       const double* C1, double* Cout, double* partials, hipStream_t s) {
-  const int32_t k = nblk_v * 16 + 16;
-  if (nblk_v < 1 || k > 128) return fail(FE_EUNSUPPORTED, "cgs_mid: %d columns at b = 16", k);
+  const int32_t kv = nblk_v * b, k = kv + b;
+  if (nblk_v < 1 || k > 128 || (b != 8 && b != 16))
+    return fail(FE_EUNSUPPORTED, "cgs_mid: %d columns at b = %d", k, b);
+  const int tiles = (kv + 15) / 16;
   const int gx = gram_sets(n);
   int64_t rows_per_wg = (n + gx - 1) / gx;
   rows_per_wg = (rows_per_wg + 15) / 16 * 16;
   const T* Vp = static_cast<const T*>(V);
   T* Wp = static_cast<T*>(W);
-#define FE_MID16(G)                                                                            \
+#define FE_MID16(G, BB)                                                                        \
   case G:                                                                                      \
-    hipLaunchKernelGGL((cgs_mid16_kernel<T, G>), dim3(gx), dim3(kGramWG), 0, s, Vp, stride, Wp, \
-                       n, C1, rows_per_wg, partials);                                          \
+    hipLaunchKernelGGL((cgs_mid16_kernel<T, G, BB>), dim3(gx), dim3(kGramWG), 0, s, Vp, stride, \
+                       Wp, n, kv, C1, rows_per_wg, partials);                                  \
     break;
-  switch (nblk_v) { FE_MID16(1) FE_MID16(2) FE_MID16(3) FE_MID16(4) FE_MID16(5) FE_MID16(6) FE_MID16(7) }
+  if (b == 16) {
+    switch (tiles) { FE_MID16(1, 16) FE_MID16(2, 16) FE_MID16(3, 16) FE_MID16(4, 16) FE_MID16(5, 16)
+                     FE_MID16(6, 16) FE_MID16(7, 16) }
+  } else if constexpr (sizeof(T) <= 4) {
+    switch (tiles) { FE_MID16(1, 8) FE_MID16(2, 8) FE_MID16(3, 8) FE_MID16(4, 8) FE_MID16(5, 8)
+                     FE_MID16(6, 8) FE_MID16(7, 8) FE_MID16(8, 8) }
+  } else {
+    if (tiles > 6) return fail(FE_EUNSUPPORTED, "cgs_mid: %d columns at b = 8 in FP64", k);
+    switch (tiles) { FE_MID16(1, 8) FE_MID16(2, 8) FE_MID16(3, 8) FE_MID16(4, 8) FE_MID16(5, 8)
+                     FE_MID16(6, 8) }
+  }
 #undef FE_MID16
   FE_HIP(hipGetLastError());
-  const int len = k * 16;
+  const int len = k * b;
   hipLaunchKernelGGL(reduce_partials, dim3((len + 63) / 64), dim3(1024), 0, s, partials, gx, len,
                      1.0, Cout);
   FE_HIP(hipGetLastError());
@@ -1527,22 +1556,24 @@ fe_status cgs_last_launch(void* V, int32_t b, int32_t ntiles, int64_t stride, in
   return fail(FE_EINVAL, "cgs_last: bad dtype");
 }
 
-bool cgs_mid_supported(int32_t b, int32_t nblk_v) {
-  if (b == 4) return nblk_v >= 1 && nblk_v * 4 + 4 <= 128;
-  if (b == 16) return nblk_v >= 1 && nblk_v * 16 + 16 <= 128;
+bool cgs_mid_supported(int32_t b, int32_t nblk_v, fe_dtype dt) {
+  if (b == 4 || b == 16) return nblk_v >= 1 && nblk_v * b + b <= 128;
+  // b = 8: up to 15 basis blocks (8 tiles) in 4- and 2-byte storage, 12 (6
+  // tiles) in FP64, whose register tiles would spill beyond
+  if (b == 8) return nblk_v >= 1 && nblk_v <= (dt == FE_F64 ? 12 : 15);
   return false;
 }
 
 fe_status cgs_mid_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk_v,
                          int64_t stride, const double* C1, double* Cout, double* partials,
                          fe_dtype dt, hipStream_t s) {
-  if (!cgs_mid_supported(b, nblk_v))
+  if (!cgs_mid_supported(b, nblk_v, dt))
     return fail(FE_EUNSUPPORTED, "cgs_mid: b=%d with %d basis blocks", b, nblk_v);
-  if (b == 16) {
+  if (b == 8 || b == 16) {
     switch (dt) {
-      case FE_F64: return cgs_mid16_t<double>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
-      case FE_F32: return cgs_mid16_t<float>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
-      case FE_BF16: return cgs_mid16_t<bf16_t>(W, n, V, nblk_v, stride, C1, Cout, partials, s);
+      case FE_F64: return cgs_mid16_t<double>(W, n, b, V, nblk_v, stride, C1, Cout, partials, s);
+      case FE_F32: return cgs_mid16_t<float>(W, n, b, V, nblk_v, stride, C1, Cout, partials, s);
+      case FE_BF16: return cgs_mid16_t<bf16_t>(W, n, b, V, nblk_v, stride, C1, Cout, partials, s);
     }
   } else {
     switch (dt) {

@@ -110,11 +110,11 @@ fe_status cgs_coef_launch(const double* C2, const double* M, int32_t k, int32_t 
 fe_status update_gram_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk,
                              int64_t blk_stride, const double* C, double* Cout, double* partials,
                              fe_dtype dt, hipStream_t s);
-// CGS2's middle step in one pass over V, at b = 4 or 16: W <- W - V[:, :b nblk_v] C1,
+// CGS2's middle step in one pass over V, at b = 4, 8 or 16: W <- W - V[:, :b nblk_v] C1,
 // then Cout ((b nblk_v + b) x b) = [V W']^T W' with the rounded W' (W its own
-// n x b block, not overlapping V).  Up to 128 columns of [V W]
-// (cgs_mid_supported); partials as for gram_launch.
-bool cgs_mid_supported(int32_t b, int32_t nblk_v);
+// n x b block, not overlapping V).  Up to 128 columns of [V W], fewer at b = 8 in
+// FP64 (cgs_mid_supported); partials as for gram_launch.
+bool cgs_mid_supported(int32_t b, int32_t nblk_v, fe_dtype dt);
 // The last pass of an orthogonalisation step at b = 16, in place: W <- [V W] Z
 // (ntiles = blocks of [V W], W the last; Z (16 ntiles) x 16 FP64) and
 // G = W^T W (16 x 16) of the rounded result; partials as for gram_launch.

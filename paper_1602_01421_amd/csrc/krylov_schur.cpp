@@ -412,7 +412,7 @@ class Solver {
     double* dC2 = dC + (size_t)(k + b) * b;
     double* flag = rec + (size_t)m * b + (size_t)b * b;
     FE_TRY(gram(nk + 1, W, dC1));
-    if (cgs_mid_supported(b, nk)) {
+    if (cgs_mid_supported(b, nk, dt)) {
       // first update and second Gram in one pass over [V W]
       prof.begin(P_GRAM);
       FE_TRY(cgs_mid_launch(W, n, b, V, nk, stride, dC1, dC2, dPart, dt, s));

@@ -351,8 +351,9 @@ def svd(args):
 def ops(args):
     """The tall-and-skinny operations alone at n rows, block width b, for basis
     sizes m (multiples of b): Gram V^T W, the block update W - V C (at b = 8
-    and 16 the MFMA contraction) and, at b = 4 and 16 with m + b <= 128, the
-    fused CGS2 middle step (W - V C and [V W]^T W in one pass)."""
+    and 16 the MFMA contraction) and, at b = 4, 8 and 16 with m + b <= 128
+    (m <= 96 at b = 8 in FP64), the fused CGS2 middle step (W - V C and
+    [V W]^T W in one pass)."""
     from . import fe as F
     import torch
     n, b = args.n, args.b
@@ -373,7 +374,7 @@ def ops(args):
             cases = [("gram", lambda: F.fe_gram(V, W, C=G[:m]), n * (m + b) * es, 2.0 * n * m * b),
                      ("update", lambda: F.fe_block_update(W, V, C), n * (m + 2 * b) * es,
                       2.0 * n * m * b)]
-            if b in (4, 16) and m + b <= 128:
+            if b in (4, 8, 16) and m + b <= 128 and not (b == 8 and es == 8 and m > 96):
                 cases.append(("cgs_mid", lambda: F.fe_block_update_gram(W, V, C, Cout=G),
                               n * (m + 2 * b) * es, 2.0 * n * (2 * m + b) * b))
             for name, fn, byts, flops in cases:
