@@ -1426,43 +1426,60 @@ fe_status cgs_mid_t(void* W, int64_t n, const void* V, int32_t nblk_v, int64_t s
   return FE_OK;
 }
 
-// The last pass of an orthogonalisation step at b = 16, in place:
-// W <- [V W] Z (Z: (16 NT) x 16, the second Gram-Schmidt update and the first
+// The last pass of an orthogonalisation step at b = 8 or 16, in place:
+// W <- [V W] Z (Z: kcols x B, the second Gram-Schmidt update and the first
 // Cholesky factor's inverse together) and, from the rounded result, the
-// partials of W^T W for the second Cholesky factor.  NT = 16-column tiles of
-// [V W] (W the last); per 16-row group a wavefront forms the product in the
-// restart contraction's layout, stores it, and passes it through a 2 KB LDS
-// tile to the Gram layout as cgs_mid16_kernel does.  The next group's loads
-// are issued before this group's store and Gram.  Every row of W is read by
-// the wavefront that writes it, before it writes it.
-template <typename T, int NT>
+// partials of W^T W for the second Cholesky factor.  [V W] has kcols columns
+// (W its last block) in NT 16-column tiles: at B = 16 one block per tile, at
+// B = 8 tile g holds blocks 2g and 2g + 1 (the second absent when the block
+// count is odd: those lanes read block 0 and meet zero rows of Z).  W's B
+// columns fill the 16 x 16 MFMA tile's first B columns, the rest are fed
+// zeros.  Per 16-row group a wavefront forms the product in the restart
+// contraction's layout, stores it, and passes it through a 2 KB LDS tile to
+// the Gram layout as cgs_mid16_kernel does.  The next group's loads are
+// issued before this group's store and Gram.  Every row of W is read by the
+// wavefront that writes it, before it writes it.
+template <typename T, int NT, int B>
 __global__ __launch_bounds__(kCgsWG) void cgs_last16_kernel(T* V, int64_t stride, int64_t n,
+                                                             int32_t kcols,
                                                              const double* __restrict__ Z,
                                                              int64_t rows_per_wg,
                                                              double* __restrict__ partials) {
   using A = typename Acc<T>::type;
   constexpr int VEC = 16 / sizeof(T) < 4 ? 16 / sizeof(T) : 4;
-  constexpr int B = 16;
+  static_assert(B == 8 || B == 16, "cgs_last16: b = 8 or 16");
+  if constexpr (B == 16) kcols = 16 * NT;  // a compile-time constant there
   constexpr int64_t kStep = (kCgsWG / 64) * kGramRowsPerIter;
-  __shared__ double Zs[16 * NT * B];
+  __shared__ double Zs[16 * NT * 16];  // Z padded to 16 NT x 16 with zeros
   __shared__ double Wt[kCgsWG / 64][256];
-  for (int i = threadIdx.x; i < 16 * NT * B; i += kCgsWG) Zs[i] = Z[i];
+  for (int i = threadIdx.x; i < 16 * NT * 16; i += kCgsWG) {
+    const int r = i >> 4, j = i & 15;
+    Zs[i] = (r < kcols && j < B) ? Z[r * B + j] : 0.0;
+  }
   __syncthreads();
-  T* W = V + (int64_t)(NT - 1) * stride;
+  T* W = V + (int64_t)(kcols / B - 1) * stride;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
   const int64_t r_begin = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t r_end = min(n, r_begin + rows_per_wg);
   const int64_t last = r_end - 1;
+  // this lane's four columns 16 g + 4 lk .. + 3 of tile g: block and offset
+  auto voff = [&](int g) -> int64_t {
+    if constexpr (B == 16) {
+      return (int64_t)g * stride + 4 * lk;
+    } else {
+      const int c = 16 * g + 4 * lk;
+      return c < kcols ? (int64_t)(2 * g + (lk >> 1)) * stride + 4 * (lk & 1) : 0;
+    }
+  };
   A v[NT][4];
   auto load_group = [&](int64_t r) {
     const int64_t ra = min(r + li, last);
 #pragma unroll
     for (int g = 0; g < NT; ++g)
 #pragma unroll
-      for (int c = 0; c < 4; c += VEC)
-        load_vec<T, VEC>(V + (int64_t)g * stride + ra * B + 4 * lk + c, v[g] + c);
+      for (int c = 0; c < 4; c += VEC) load_vec<T, VEC>(V + voff(g) + ra * B + c, v[g] + c);
   };
   int64_t r0 = r_begin + wave * kGramRowsPerIter;
   if (r0 < r_end) load_group(r0);
@@ -1474,12 +1491,12 @@ __global__ __launch_bounds__(kCgsWG) void cgs_last16_kernel(T* V, int64_t stride
 #pragma unroll
       for (int st = 0; st < 4; ++st)
         u = __builtin_amdgcn_mfma_f64_16x16x4f64((double)v[g][st],
-                                                 Zs[(16 * g + 4 * lk + st) * B + li], u, 0, 0, 0);
+                                                 Zs[(16 * g + 4 * lk + st) * 16 + li], u, 0, 0, 0);
     load_group(r0 + kStep);  // past r_end: re-reads the last row, unused
 #pragma unroll
     for (int reg = 0; reg < 4; ++reg) {
       const int64_t row = r0 + 4 * reg + lk;
-      const bool rv = row < r_end;
+      const bool rv = row < r_end && li < B;
       const T t = to_storage<T, double>(u[reg]);
       double wr;
       if constexpr (sizeof(T) == 2)
@@ -1512,46 +1529,63 @@ __global__ __launch_bounds__(kCgsWG) void cgs_last16_kernel(T* V, int64_t stride
   double* out = partials + (int64_t)blockIdx.x * B * B;
   for (int idx = threadIdx.x; idx < 4 * 64; idx += kCgsWG) {
     const int l = idx & 63, r = idx >> 6;
-    out[(4 * r + (l >> 4)) * B + (l & 15)] = red[r][l];
+    const int i = 4 * r + (l >> 4), j = l & 15;
+    if (i < B && j < B) out[i * B + j] = red[r][l];
   }
 }
 
 template <typename T>
-fe_status cgs_last16_t(void* V, int32_t ntiles, int64_t stride, int64_t n, const double* Z,
-                       double* G, double* partials, hipStream_t s) {
+fe_status cgs_last16_t(void* V, int32_t b, int32_t nblocks, int64_t stride, int64_t n,
+                       const double* Z, double* G, double* partials, hipStream_t s) {
   const int gx = cgs_sets(n);
   int64_t rows_per_wg = (n + gx - 1) / gx;
   rows_per_wg = (rows_per_wg + 15) / 16 * 16;
   T* Vp = static_cast<T*>(V);
-#define FE_LAST16(NT)                                                                           \
-  case NT:                                                                                      \
-    hipLaunchKernelGGL((cgs_last16_kernel<T, NT>), dim3(gx), dim3(kCgsWG), 0, s, Vp, stride, n, \
-                       Z, rows_per_wg, partials);                                               \
+  const int32_t kcols = nblocks * b;
+  const int tiles = (kcols + 15) / 16;
+#define FE_LAST16(NT, BB)                                                                      \
+  case NT:                                                                                     \
+    hipLaunchKernelGGL((cgs_last16_kernel<T, NT, BB>), dim3(gx), dim3(kCgsWG), 0, s, Vp, stride, \
+                       n, kcols, Z, rows_per_wg, partials);                                    \
     break;
-  switch (ntiles) {
-    FE_LAST16(2) FE_LAST16(3) FE_LAST16(4) FE_LAST16(5) FE_LAST16(6) FE_LAST16(7) FE_LAST16(8)
-    default:
-      return fail(FE_EUNSUPPORTED, "cgs_last: %d tiles at b = 16", ntiles);
+  if (b == 16) {
+    switch (tiles) {
+      FE_LAST16(2, 16) FE_LAST16(3, 16) FE_LAST16(4, 16) FE_LAST16(5, 16) FE_LAST16(6, 16)
+      FE_LAST16(7, 16) FE_LAST16(8, 16)
+      default:
+        return fail(FE_EUNSUPPORTED, "cgs_last: %d blocks at b = 16", nblocks);
+    }
+  } else {
+    switch (tiles) {
+      FE_LAST16(1, 8) FE_LAST16(2, 8) FE_LAST16(3, 8) FE_LAST16(4, 8) FE_LAST16(5, 8)
+      FE_LAST16(6, 8) FE_LAST16(7, 8) FE_LAST16(8, 8)
+      default:
+        return fail(FE_EUNSUPPORTED, "cgs_last: %d blocks at b = 8", nblocks);
+    }
   }
 #undef FE_LAST16
   FE_HIP(hipGetLastError());
-  hipLaunchKernelGGL(reduce_partials, dim3((256 + 63) / 64), dim3(1024), 0, s, partials, gx, 256,
-                     1.0, G);
+  hipLaunchKernelGGL(reduce_partials, dim3((b * b + 63) / 64), dim3(1024), 0, s, partials, gx,
+                     b * b, 1.0, G);
   FE_HIP(hipGetLastError());
   return FE_OK;
 }
 
-bool cgs_last_supported(int32_t b, int32_t ntiles) { return b == 16 && ntiles >= 2 && ntiles <= 8; }
+bool cgs_last_supported(int32_t b, int32_t nblocks) {
+  if (b == 16) return nblocks >= 2 && nblocks <= 8;
+  if (b == 8) return nblocks >= 2 && nblocks <= 16;
+  return false;
+}
 
-fe_status cgs_last_launch(void* V, int32_t b, int32_t ntiles, int64_t stride, int64_t n,
+fe_status cgs_last_launch(void* V, int32_t b, int32_t nblocks, int64_t stride, int64_t n,
                           const double* Z, double* G, double* partials, fe_dtype dt,
                           hipStream_t s) {
-  if (!cgs_last_supported(b, ntiles))
-    return fail(FE_EUNSUPPORTED, "cgs_last: b=%d with %d tiles", b, ntiles);
+  if (!cgs_last_supported(b, nblocks))
+    return fail(FE_EUNSUPPORTED, "cgs_last: b=%d with %d blocks", b, nblocks);
   switch (dt) {
-    case FE_F64: return cgs_last16_t<double>(V, ntiles, stride, n, Z, G, partials, s);
-    case FE_F32: return cgs_last16_t<float>(V, ntiles, stride, n, Z, G, partials, s);
-    case FE_BF16: return cgs_last16_t<bf16_t>(V, ntiles, stride, n, Z, G, partials, s);
+    case FE_F64: return cgs_last16_t<double>(V, b, nblocks, stride, n, Z, G, partials, s);
+    case FE_F32: return cgs_last16_t<float>(V, b, nblocks, stride, n, Z, G, partials, s);
+    case FE_BF16: return cgs_last16_t<bf16_t>(V, b, nblocks, stride, n, Z, G, partials, s);
   }
   return fail(FE_EINVAL, "cgs_last: bad dtype");
 }

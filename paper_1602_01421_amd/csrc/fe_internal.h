@@ -115,11 +115,12 @@ fe_status update_gram_launch(void* W, int64_t n, int32_t b, const void* V, int32
 // n x b block, not overlapping V).  Up to 128 columns of [V W], fewer at b = 8 in
 // FP64 (cgs_mid_supported); partials as for gram_launch.
 bool cgs_mid_supported(int32_t b, int32_t nblk_v, fe_dtype dt);
-// The last pass of an orthogonalisation step at b = 16, in place: W <- [V W] Z
-// (ntiles = blocks of [V W], W the last; Z (16 ntiles) x 16 FP64) and
-// G = W^T W (16 x 16) of the rounded result; partials as for gram_launch.
-bool cgs_last_supported(int32_t b, int32_t ntiles);
-fe_status cgs_last_launch(void* V, int32_t b, int32_t ntiles, int64_t blk_stride, int64_t n,
+// The last pass of an orthogonalisation step at b = 8 or 16, in place:
+// W <- [V W] Z (nblocks = blocks of [V W], W the last, up to 128 columns;
+// Z (b nblocks) x b FP64) and G = W^T W (b x b) of the rounded result;
+// partials as for gram_launch.
+bool cgs_last_supported(int32_t b, int32_t nblocks);
+fe_status cgs_last_launch(void* V, int32_t b, int32_t nblocks, int64_t blk_stride, int64_t n,
                           const double* Z, double* G, double* partials, fe_dtype dt,
                           hipStream_t s);
 fe_status cgs_mid_launch(void* W, int64_t n, int32_t b, const void* V, int32_t nblk_v,

@@ -292,12 +292,14 @@ def test_start_block_with_nan_and_repeated_columns(fe):
     assert np.allclose(r.evals, ref.evals, rtol=1e-10)
 
 
-@pytest.mark.parametrize("nev,b,m", [(4, 1, 24), (6, 2, 32), (8, 16, 64), (8, 4, 112)])
+@pytest.mark.parametrize("nev,b,m", [(4, 1, 24), (6, 2, 32), (8, 16, 64), (8, 4, 112),
+                                     (8, 8, 112)])
 def test_block_widths_fp64_match_oracle(fe, nev, b, m):
-    """Block widths 1, 2 (element-load Gram), 16 (widest factor kernels) and
-    4 with m 112 (the fused CGS2 middle step up to 116 columns): FP64
-    storage, same start block as the oracle: same products, eigenvalues
-    within 1e-10."""
+    """Block widths 1, 2 (element-load Gram), 16 (widest factor kernels),
+    4 with m 112 (the fused CGS2 middle step up to 116 columns) and 8 with
+    m 112 (the fused middle step up to 12 basis blocks in FP64, the separate
+    update and Gram at 13): FP64 storage, same start block as the oracle:
+    same products, eigenvalues within 1e-10."""
     g = S.chung_lu_edges(30000, alpha=2.2, mean_deg=12, seed=17)
     A, rp, ci = setup(fe, g)
     X0 = S.normal((A.n, b), seed=8)
