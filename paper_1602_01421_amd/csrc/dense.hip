@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kGramWG) void gram_wide_kernel(const T* __restrict_
   constexpr int VEC = 16 / sizeof(T) < 4 ? 16 / sizeof(T) : 4;  // 4 elements per load group
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kk = lane >> 4, blk = (lane >> 2) & 3, x = lane & 3;
-  const int p_base = blockIdx.y * (16 * kGramPG);
+  const int p_base = blockIdx.y * (16 * NPG);
   const int q_base = blockIdx.z * (4 * NQG);
   const int nqg = min(NQG, (b - q_base + 3) / 4);
   // column group of this lane's quad: 4 consecutive columns inside one block
@@ -723,13 +723,26 @@ fe_status gram_t(const void* V, int32_t nblk, int64_t stride, const void* W, int
     }
   } else if (b % 4 == 0) {  // 16-byte row loads and quad transposes
     // NPG: 16-column V groups per slice, a template parameter so that no MFMA
-    // chain is guarded (groups past k are fed zeros)
-    const int npg = std::min(kGramPG, (k + 15) / 16);
+    // chain is guarded (groups past k are fed zeros); the groups split evenly
+    // over the slices, up to 8 per slice at b = 4 and 8 in 4- and 2-byte
+    // storage (one pass over W up to 128 columns: each slice reads W), else 4
+    constexpr int max_pg = sizeof(T) <= 4 ? 8 : kGramPG;
+    const int groups = (k + 15) / 16;
+    const int cap = b <= 8 ? max_pg : kGramPG;
+    const int slices = (groups + cap - 1) / cap;
+    const int npg = (groups + slices - 1) / slices;
+    grid.y = slices;
 #define FE_GRAM_W(Q)                                                                          \
   if (npg == 1) FE_GRAM2(gram_wide_kernel, Q, 1);                                             \
   else if (npg == 2) FE_GRAM2(gram_wide_kernel, Q, 2);                                        \
   else if (npg == 3) FE_GRAM2(gram_wide_kernel, Q, 3);                                        \
-  else FE_GRAM2(gram_wide_kernel, Q, 4);
+  else if (npg == 4) FE_GRAM2(gram_wide_kernel, Q, 4);                                        \
+  else if constexpr (max_pg == 8 && Q <= 2) {                                                 \
+    if (npg == 5) FE_GRAM2(gram_wide_kernel, Q, 5);                                           \
+    else if (npg == 6) FE_GRAM2(gram_wide_kernel, Q, 6);                                      \
+    else if (npg == 7) FE_GRAM2(gram_wide_kernel, Q, 7);                                      \
+    else FE_GRAM2(gram_wide_kernel, Q, 8);                                                    \
+  }
     if (b == 4) { FE_GRAM_W(1) }
     else if (b == 8) { FE_GRAM_W(2) }
     else { FE_GRAM_W(4) }  // 16 W columns per z-slice

@@ -29,8 +29,13 @@ def host(t):
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("n,nblk,b", [(1, 1, 1), (37, 3, 4), (1000, 13, 4), (4097, 6, 8),
                                       (777, 2, 16), (5000, 5, 3), (300, 1, 64), (70001, 12, 4),
-                                      (1001, 5, 16), (3333, 9, 8), (15, 8, 16)])
+                                      (1001, 5, 16), (3333, 9, 8), (15, 8, 16), (2001, 17, 4),
+                                      (4099, 31, 4), (999, 11, 8), (20003, 16, 8), (17, 15, 8),
+                                      (3001, 40, 4), (1003, 24, 8)])
 def test_gram_small_int_bitwise(fe, dt, n, nblk, b):
+    """Every column-group count per slice and slices split evenly (b = 4, 8:
+    up to 8 groups of 16 columns per slice in 4- and 2-byte storage, 4 in
+    FP64), ragged and tiny row counts: exact on small integers."""
     V = S.small_ints((nblk, n, b), seed=1, lo=-4, hi=4)
     W = S.small_ints((n, b), seed=2, lo=-4, hi=4)
     C = host(fe.fe_gram(dev(V, DT[dt]), dev(W, DT[dt]), alpha=2.0))
