@@ -179,14 +179,17 @@ __global__ __launch_bounds__(kGramWG) void gram_wide_kernel(const T* __restrict_
   const int p_base = blockIdx.y * (16 * NPG);
   const int q_base = blockIdx.z * (4 * NQG);
   const int nqg = min(NQG, (b - q_base + 3) / 4);
-  // column group of this lane's quad: 4 consecutive columns inside one block
+  // column group of this lane's quad: 4 consecutive columns inside one block;
+  // quads past k load the last 4 columns (k - 4.., in this slice, loaded by
+  // the quad that owns them: the same cache lines) and discard the values
   int64_t aoff[NPG];
   bool aval[NPG];
 #pragma unroll
   for (int pg = 0; pg < NPG; ++pg) {
     const int c0 = p_base + pg * 16 + 4 * blk;
     aval[pg] = c0 < k;
-    aoff[pg] = aval[pg] ? (int64_t)(c0 / b) * stride + (c0 % b) : 0;
+    const int cc = aval[pg] ? c0 : k - 4;
+    aoff[pg] = (int64_t)(cc / b) * stride + (cc % b);
   }
   int boff[NQG];
   bool bval[NQG];
